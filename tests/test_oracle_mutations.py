@@ -1,0 +1,154 @@
+"""Plant plausible mistakes in the oracle (CPU only) and check that at least
+one pin fails for each: evidence that the pins constrain every part."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.basis as OB
+import oracle.ritz as OR
+import oracle.sstep as OS
+import pins
+
+
+def _mut_alg3_wrong_zeta(mp):
+    orig = OR.MaxRitzEstimate.step
+
+    def step(self, eta, zeta_next):
+        return orig(self, eta, self.zeta)          # a = eta^2 + zeta_l^2 instead of zeta_{l+1}
+    mp.setattr(OR.MaxRitzEstimate, "step", step)
+
+
+def _mut_alg4_sign(mp):
+    orig = OR.MinRitzEstimate.step
+
+    def step(self, eta, zeta_next):
+        self.d = -self.d                              # coupling sign lost
+        return orig(self, eta, zeta_next)
+    mp.setattr(OR.MinRitzEstimate, "step", step)
+
+
+def _mut_alg4_drop_one(mp):
+    def step(self, eta, zeta_next):
+        d = -(eta / zeta_next) * (self.g * self.d + self.h * self.a)
+        a = (eta * eta * self.a) / (zeta_next * zeta_next)    # "+1" dropped
+        chi = math.sqrt((self.omega - a) ** 2 + 4.0 * d * d)
+        h = math.sqrt(max(0.0, 0.5 * (1.0 - (self.omega - a) / chi))) if chi else 0.0
+        self.omega += chi * h * h
+        self.g = math.sqrt(max(0.0, 1.0 - h * h)); self.h = abs(h) * (1 if d >= 0 else -1)
+        self.d, self.a = d, a
+        return 1.0 / self.omega
+    mp.setattr(OR.MinRitzEstimate, "step", step)
+
+
+def _mut_cheb_printed_mu(mp):
+    def cheb(lmin, lmax, s):
+        c, d = 0.5 * (lmin + lmax), lmax - lmin
+        g = np.full(s, 0.5 * d); g[0] = d
+        return np.full(s, c), g, np.full(max(s - 1, 0), 2.0 * d)
+    mp.setattr(O, "params_chebyshev", cheb); mp.setattr(OB, "params_chebyshev", cheb)
+
+
+def _mut_drop_mu_term(mp):
+    def cols(A, v, nlev, theta, gamma, mu):
+        out = np.empty((v.size, nlev + 1)); out[:, 0] = v
+        for l in range(1, nlev + 1):
+            out[:, l] = (A @ out[:, l - 1] - theta[l - 1] * out[:, l - 1]) / gamma[l - 1]
+        return out
+    mp.setattr(O, "polynomial_columns", cols); mp.setattr(OB, "polynomial_columns", cols)
+
+
+def _mut_B_transposed(mp):
+    orig = OB.change_of_basis
+    f = lambda s, prm: orig(s, prm).T
+    mp.setattr(O, "change_of_basis", f); mp.setattr(OB, "change_of_basis", f)
+    mp.setattr(OS, "change_of_basis", f)
+
+
+def _mut_sub_prefix(mp):
+    f = lambda sbar, l: np.arange(2 * l + 1)
+    mp.setattr(O, "sub_indices", f); mp.setattr(OB, "sub_indices", f); mp.setattr(OS, "sub_indices", f)
+
+
+def _mut_psi_sign(mp):
+    f = lambda psi, beta: psi / (psi - beta)
+    mp.setattr(O, "psi_update", f); mp.setattr(OR, "psi_update", f); mp.setattr(OS, "psi_update", f)
+
+
+def _mut_T_diag(mp):
+    def T(alphas, betas, i=None):
+        i = len(alphas) if i is None else i
+        M = np.zeros((i, i))
+        for j in range(i):
+            M[j, j] = 1.0 / alphas[j]                  # beta_{j-1}/alpha_{j-1} dropped
+            if j + 1 < i:
+                M[j, j + 1] = M[j + 1, j] = math.sqrt(betas[j]) / alphas[j]
+        return M
+    mp.setattr(O, "lanczos_tridiagonal", T); mp.setattr(OR, "lanczos_tridiagonal", T)
+
+
+def _mut_leja_tie_max(mp):
+    orig = OB.leja_reference_points
+
+    def f(count):
+        t = orig(count).copy()
+        if count > 3:
+            t[3] = -t[3]                                # tie broken the other way
+        return t
+    mp.setattr(O, "leja_reference_points", f); mp.setattr(OB, "leja_reference_points", f)
+
+
+def _mut_newton_swap(mp):
+    orig = OB.params_newton
+
+    def f(lmin, lmax, s):
+        th, g, m = orig(lmin, lmax, s)
+        th = th.copy(); th[0], th[1] = th[1], th[0]
+        return th, g, m
+    mp.setattr(O, "params_newton", f); mp.setattr(OB, "params_newton", f)
+
+
+def _mut_alpha_without_B(mp):
+    f = lambda s, prm: np.eye(2 * s + 1)
+    mp.setattr(OS, "change_of_basis", f)
+
+
+def _mut_hscg_beta(mp):
+    orig = O.hscg
+
+    def f(A, b, x0=None, tol=1e-10, max_iters=None, record=False, record_vectors=False):
+        x, info = orig(A, b, x0, tol, max_iters, record, record_vectors)
+        info["betas"] = [bb * 1.001 for bb in info["betas"]]
+        return x, info
+    mp.setattr(O, "hscg", f)
+
+
+MUTATIONS = {
+    "alg3_wrong_zeta": _mut_alg3_wrong_zeta,
+    "alg4_coupling_sign": _mut_alg4_sign,
+    "alg4_drop_one": _mut_alg4_drop_one,
+    "chebyshev_printed_mu": _mut_cheb_printed_mu,
+    "basis_drop_mu_term": _mut_drop_mu_term,
+    "B_transposed": _mut_B_transposed,
+    "sub_indices_prefix": _mut_sub_prefix,
+    "psi_sign": _mut_psi_sign,
+    "T_diag_term": _mut_T_diag,
+    "leja_tie_other_way": _mut_leja_tie_max,
+    "newton_first_two_swapped": _mut_newton_swap,
+    "alpha_without_B": _mut_alpha_without_B,
+    "hscg_beta_scaled": _mut_hscg_beta,
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, monkeypatch):
+    MUTATIONS[name](monkeypatch)
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin()
+        except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError, KeyError,
+                IndexError, np.linalg.LinAlgError):
+            failed.append(pin.__name__)
+    assert failed, f"no pin caught mutation {name}"
