@@ -51,7 +51,8 @@ def _kappa_sub(G, idx) -> float:
 
 
 def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-10,
-                      basis="chebyshev", max_outer=None, max_iters=None, record=True):
+                      basis="chebyshev", max_outer=None, max_iters=None, record=True,
+                      record_gram=False):
     """Solve A x = b by the improved adaptive s-step CG (Algorithm 5).
 
     Parameters follow the algorithm's inputs: sigma = ``s_max``,
@@ -59,6 +60,8 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
     eps* = ``tol``; ``basis`` is "chebyshev", "newton" or "monomial" (the
     last keeps the monomial basis throughout).
     Returns (x, info); ``info["trace"]`` has one record per outer loop.
+    With ``record_gram`` each record also keeps G (paper order) and the
+    carried state at the start of the loop (for step-by-step comparisons).
     """
     A = A.tocsr() if hasattr(A, "tocsr") else A
     b = np.asarray(b, dtype=np.float64)
@@ -99,6 +102,16 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
         Y = sstep_basis(A, p, r, sbar, params)
         G = Y.T @ Y
         rec = {"k": k, "sbar": sbar, "m": m, "c_in": c}
+        if record_gram:
+            rec["G"] = G.copy()
+            rec["state_in"] = {
+                "m": m, "c": c, "psi": psi, "alpha_prev": alpha_prev, "beta_prev": beta_prev,
+                "mt_max": None if mt_max is None else (mt_max.omega, mt_max.h, mt_max.zeta),
+                "mt_min": None if mt_min is None else (mt_min.omega, mt_min.a, mt_min.d,
+                                                       mt_min.g, mt_min.h),
+                "lmin": lmin, "lmax": lmax,
+                "params": tuple(np.array(q, dtype=np.float64) for q in params),
+            }
         if not np.all(np.isfinite(G)):
             outcome = Outcome.DIVERGED
             info["trace"].append(rec)
@@ -171,6 +184,9 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
                 break
         rec.update(sk=sk, phi=phi, c=c, lmin=lmin, lmax=lmax, psi=psi,
                    relres_updated=math.sqrt(rGr) / nb, candidate=candidate)
+        if record_gram:
+            rec.update(xc=xc.copy(), rc=rc.copy(), pc=pc.copy(),
+                       alphas=info["alphas"][m:m + sk], betas=info["betas"][m:m + sk])
         if outcome is not None and outcome != Outcome.CONVERGED:
             info["trace"].append(rec)
             break

@@ -1,0 +1,732 @@
+// C ABI of the library (include/assg.h): argument checks, workspace, the
+// host side of the outer loop (enqueue only; every decision is made on the
+// device), timing and result copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "assg.h"
+#include "ctl.hpp"
+#include "launch.hpp"
+
+using namespace assg;
+
+struct assg_handle_s {
+  int device = 0;
+  int cus = 256;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_start = nullptr, ev_stop = nullptr;
+  Ctl* d_ctl = nullptr;
+  Ctl* h_ctl = nullptr;          // pinned mirror
+  int32_t* h_status = nullptr;   // pinned
+  assg_trace_t* d_trace = nullptr;
+  int64_t trace_cap = 0;
+  int64_t trace_count = 0;
+  void* ws = nullptr;            // owned workspace
+  size_t ws_bytes = 0;
+  // analysis
+  int64_t an_n = -1, an_nnz = -1;
+  const int32_t* an_rp = nullptr;
+  int lpr = 8;
+  int gram_blocks[MAXS + 1] = {0};
+  double leja[MAXS];
+  std::string err;
+  std::vector<hipEvent_t> evpool;
+};
+
+namespace {
+
+// Leja points of [-1, 1] in the order of (2.7): t0 = 1, t1 = -1, then each
+// point maximizes prod |t - t_m|.  In every gap between consecutive points
+// the logarithmic derivative sum 1/(t - t_m) decreases from +inf to -inf;
+// its zero (bisection to the last bit) is the gap's maximizer.  The largest
+// product wins; products equal to a relative 1e-9 count as ties, broken
+// towards the smaller t.
+void leja_table(double* t, int count) {
+  t[0] = 1.0;
+  if (count > 1) t[1] = -1.0;
+  for (int l = 2; l < count; ++l) {
+    std::vector<double> s(t, t + l);
+    std::sort(s.begin(), s.end());
+    std::vector<double> cand, val;
+    for (int g = 0; g + 1 < l; ++g) {
+      double lo = s[g], hi = s[g + 1];
+      for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double f = 0.0;
+        for (int q = 0; q < l; ++q) f += 1.0 / (mid - s[q]);
+        if (f > 0.0) lo = mid; else hi = mid;
+      }
+      const double tc = 0.5 * (lo + hi);
+      double v = 0.0;
+      for (int q = 0; q < l; ++q) v += std::log(std::fabs(tc - s[q]));
+      cand.push_back(tc);
+      val.push_back(v);
+    }
+    double vmax = -INFINITY;
+    for (double v : val) vmax = std::max(vmax, v);
+    double best = INFINITY;
+    for (size_t q = 0; q < cand.size(); ++q)
+      if (val[q] >= vmax - 1e-9) best = std::min(best, cand[q]);
+    t[l] = best;
+  }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct WsLayout {
+  int64_t ld;
+  size_t pairs_off, plast_off, rowpart_off, grampart_off, total;
+};
+
+WsLayout ws_layout(int64_t n, int32_t s_max) {
+  WsLayout w;
+  w.ld = (int64_t)align_up((size_t)n, 32);
+  const size_t vec = (size_t)w.ld * sizeof(double);
+  const size_t basis = std::max((size_t)s_max * 2 * vec + vec, 3 * vec);
+  w.pairs_off = 0;
+  w.plast_off = (size_t)s_max * 2 * vec;
+  w.rowpart_off = align_up(basis, 256);
+  w.grampart_off = w.rowpart_off + align_up(2 * MAX_ROW_BLOCKS * sizeof(double), 256);
+  const size_t np = (size_t)(2 * s_max + 1) * (2 * s_max + 2) / 2;
+  w.total = w.grampart_off + align_up(np * 4096 * sizeof(double), 256);
+  return w;
+}
+
+assg_status_t fail(assg_handle_t h, assg_status_t st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL(h, call)                                                         \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((h), ASSG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool csr_ok(const assg_csr_t* A) {
+  return A && A->n >= 1 && A->nnz >= 1 && A->nnz < (int64_t(1) << 31) && A->row_ptr &&
+         A->col_idx && A->val;
+}
+
+assg_status_t check_analyzed(assg_handle_t h, const assg_csr_t* A) {
+  if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
+  if (A->n != h->an_n || A->nnz != h->an_nnz || A->row_ptr != h->an_rp)
+    return fail(h, ASSG_ERR_NOT_ANALYZED, "matrix not analyzed (call assg_analyze)");
+  return ASSG_OK;
+}
+
+assg_status_t get_workspace(assg_handle_t h, int64_t n, int32_t s_max, void* ws, size_t bytes,
+                            char** base, WsLayout* lay) {
+  *lay = ws_layout(n, s_max);
+  if (ws) {
+    if (bytes < lay->total) return fail(h, ASSG_ERR_INVALID_ARG, "workspace too small");
+    *base = static_cast<char*>(ws);
+    return ASSG_OK;
+  }
+  if (h->ws_bytes < lay->total) {
+    if (h->ws) {
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      HIP_OR_FAIL(h, hipFree(h->ws));
+      h->ws = nullptr;
+      h->ws_bytes = 0;
+    }
+    if (hipMalloc(&h->ws, lay->total) != hipSuccess) {
+      h->ws = nullptr;
+      return fail(h, ASSG_ERR_ALLOC, "workspace allocation failed");
+    }
+    h->ws_bytes = lay->total;
+  }
+  *base = static_cast<char*>(h->ws);
+  return ASSG_OK;
+}
+
+void init_ctl(assg_handle_t h, Ctl* c, int mode) {
+  std::memset(c, 0, sizeof(Ctl));
+  c->status = ST_RUNNING;
+  c->pending = ST_RUNNING;
+  c->mode = mode;
+  c->psi = 1.0;
+  c->c = 1.0 / std::sqrt(UNIT_ROUNDOFF);   // c_1 = eps^{-1/2}
+  c->lmin = NAN;
+  c->lmax = NAN;
+  c->alpha_prev = NAN;
+  c->beta_prev = NAN;
+  c->best_true = INFINITY;
+  c->relres_true = -1.0;
+  for (int l = 0; l < MAXS; ++l) {
+    c->theta[l] = 0.0;
+    c->gamma[l] = 1.0;
+    c->mu[l] = 0.0;
+    c->leja[l] = h->leja[l];
+  }
+}
+
+// b = 0: the solution is x = 0 (nothing to iterate).  Reads ||b|| computed
+// by the setup kernel; returns true (with *st set) when the solve is done.
+bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_status_t* st) {
+  double* nbh = reinterpret_cast<double*>(h->h_status + 8);
+  *st = ASSG_OK;
+  if (hipMemcpyAsync(nbh, &h->d_ctl->nb, sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    *st = fail(h, ASSG_ERR_HIP, "reading ||b|| failed");
+    return true;
+  }
+  if (*nbh != 0.0) return false;
+  if (hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    *st = fail(h, ASSG_ERR_HIP, "clearing x failed");
+    return true;
+  }
+  info->outcome = ASSG_CONVERGED;
+  info->relres_true = 0.0;
+  info->relres_updated = 0.0;
+  return true;
+}
+
+hipEvent_t pool_event(assg_handle_t h, size_t i) {
+  while (h->evpool.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->evpool.push_back(e);
+  }
+  return h->evpool[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+assg_status_t assg_default_opts(assg_opts_t* o) {
+  if (!o) return ASSG_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->s_max = 10;
+  o->s_init = 10;
+  o->growth = 10;
+  o->basis = ASSG_BASIS_CHEBYSHEV;
+  o->tol = 1e-10;
+  o->max_outer = 0;
+  o->max_iters = 0;
+  o->record_trace = 0;
+  o->time_kernels = 0;
+  return ASSG_OK;
+}
+
+const char* assg_status_string(assg_status_t s) {
+  switch (s) {
+    case ASSG_OK: return "ok";
+    case ASSG_ERR_INVALID_ARG: return "invalid argument";
+    case ASSG_ERR_HIP: return "HIP error";
+    case ASSG_ERR_ALLOC: return "allocation failed";
+    case ASSG_ERR_UNSUPPORTED: return "unsupported device";
+    case ASSG_ERR_NOT_ANALYZED: return "matrix not analyzed";
+  }
+  return "unknown status";
+}
+
+const char* assg_last_error(assg_handle_t h) { return h ? h->err.c_str() : ""; }
+
+int32_t assg_struct_sizes(int64_t* sizes, int32_t cap) {
+  const int64_t s[] = {(int64_t)sizeof(assg_opts_t),        (int64_t)sizeof(assg_info_t),
+                       (int64_t)sizeof(assg_trace_t),       (int64_t)sizeof(assg_block_state_t),
+                       (int64_t)sizeof(assg_block_result_t), (int64_t)sizeof(assg_csr_t)};
+  int32_t k = 0;
+  for (; k < cap && k < 6; ++k) sizes[k] = s[k];
+  return k;
+}
+
+assg_status_t assg_basis_params(int32_t kind, double lmin, double lmax, int32_t s, double* theta,
+                                double* gamma, double* mu) {
+  if (s < 1 || s > ASSG_MAX_S || !theta || !gamma || (s > 1 && !mu)) return ASSG_ERR_INVALID_ARG;
+  if (kind != ASSG_BASIS_MONOMIAL && kind != ASSG_BASIS_NEWTON && kind != ASSG_BASIS_CHEBYSHEV)
+    return ASSG_ERR_INVALID_ARG;
+  if (kind != ASSG_BASIS_MONOMIAL && !(lmin < lmax && std::isfinite(lmin) && std::isfinite(lmax)))
+    return ASSG_ERR_INVALID_ARG;
+  double t[MAXS];
+  leja_table(t, MAXS);
+  double th[MAXS], ga[MAXS], m[MAXS];
+  basis_params(kind, lmin, lmax, s, t, th, ga, m);
+  for (int l = 0; l < s; ++l) {
+    theta[l] = th[l];
+    gamma[l] = ga[l];
+    if (l + 1 < s) mu[l] = m[l];
+  }
+  return ASSG_OK;
+}
+
+assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes) {
+  if (n < 1 || s_max < 1 || s_max > ASSG_MAX_S || !bytes) return ASSG_ERR_INVALID_ARG;
+  *bytes = ws_layout(n, s_max).total;
+  return ASSG_OK;
+}
+
+assg_status_t assg_create(assg_handle_t* out, void* stream) {
+  if (!out) return ASSG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ASSG_ERR_UNSUPPORTED;
+  assg_handle_t h = new assg_handle_s();
+  HIP_OR_FAIL(h, hipGetDevice(&h->device));
+  hipDeviceProp_t prop;
+  HIP_OR_FAIL(h, hipGetDeviceProperties(&prop, h->device));
+  h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  h->user_stream = static_cast<hipStream_t>(stream);
+  HIP_OR_FAIL(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  HIP_OR_FAIL(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+  HIP_OR_FAIL(h, hipEventCreate(&h->ev_start));
+  HIP_OR_FAIL(h, hipEventCreate(&h->ev_stop));
+  HIP_OR_FAIL(h, hipMalloc(&h->d_ctl, sizeof(Ctl)));
+  HIP_OR_FAIL(h, hipHostMalloc(&h->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  HIP_OR_FAIL(h, hipHostMalloc(&h->h_status, 128, hipHostMallocDefault));
+  leja_table(h->leja, MAXS);
+  for (int s = 1; s <= MAXS; ++s) h->gram_blocks[s] = last_gram_blocks(s, h->cus);
+  *out = h;
+  return ASSG_OK;
+}
+
+assg_status_t assg_destroy(assg_handle_t h) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->d_trace) (void)hipFree(h->d_trace);
+  if (h->d_ctl) (void)hipFree(h->d_ctl);
+  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->h_status) (void)hipHostFree(h->h_status);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_start) (void)hipEventDestroy(h->ev_start);
+  if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return ASSG_OK;
+}
+
+assg_status_t assg_set_stream(assg_handle_t h, void* stream) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  h->user_stream = static_cast<hipStream_t>(stream);
+  return ASSG_OK;
+}
+
+assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
+  std::vector<int32_t> rp((size_t)A->n + 1);
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  HIP_OR_FAIL(h, hipMemcpyAsync(rp.data(), A->row_ptr, rp.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (rp[0] != 0 || (int64_t)rp[A->n] != A->nnz)
+    return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
+  for (int64_t i = 0; i < A->n; ++i)
+    if (rp[i + 1] < rp[i]) return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr must be nondecreasing");
+  h->lpr = pick_lpr(A->n, A->nnz);
+  h->an_n = A->n;
+  h->an_nnz = A->nnz;
+  h->an_rp = A->row_ptr;
+  h->err.clear();
+  return ASSG_OK;
+}
+
+assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, double* y) {
+  if (!h || !x || !y) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  assg_status_t st = check_analyzed(h, A);
+  if (st != ASSG_OK) return st;
+  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  launch_spmv(h->stream, Av, h->lpr, x, y);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return ASSG_OK;
+}
+
+static assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o) {
+  if (!o) return fail(h, ASSG_ERR_INVALID_ARG, "null options");
+  if (o->s_max < 1 || o->s_max > ASSG_MAX_S)
+    return fail(h, ASSG_ERR_INVALID_ARG, "s_max must be in 1..ASSG_MAX_S");
+  if (o->s_init < 1 || o->s_init > o->s_max)
+    return fail(h, ASSG_ERR_INVALID_ARG, "s_init must be in 1..s_max");
+  if (o->growth < 1) return fail(h, ASSG_ERR_INVALID_ARG, "growth must be >= 1");
+  if (o->basis != ASSG_BASIS_MONOMIAL && o->basis != ASSG_BASIS_NEWTON &&
+      o->basis != ASSG_BASIS_CHEBYSHEV)
+    return fail(h, ASSG_ERR_INVALID_ARG, "unknown basis");
+  if (!(o->tol > 0.0 && o->tol < 1.0)) return fail(h, ASSG_ERR_INVALID_ARG, "tol must be in (0,1)");
+  if (o->max_outer < 0 || o->max_iters < 0)
+    return fail(h, ASSG_ERR_INVALID_ARG, "iteration caps must be >= 0");
+  return ASSG_OK;
+}
+
+assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                         const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
+                         assg_info_t* info) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!b || !x || !info) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  assg_status_t st = validate_opts(h, opts);
+  if (st != ASSG_OK) return st;
+  st = check_analyzed(h, A);
+  if (st != ASSG_OK) return st;
+  std::memset(info, 0, sizeof(*info));
+  const int64_t n = A->n;
+  const int sigma = opts->s_max;
+  char* base = nullptr;
+  WsLayout lay;
+  st = get_workspace(h, n, sigma, workspace, workspace_bytes, &base, &lay);
+  if (st != ASSG_OK) return st;
+  double2* pairs = reinterpret_cast<double2*>(base + lay.pairs_off);
+  double* plast = reinterpret_cast<double*>(base + lay.plast_off);
+  double* rowpart = reinterpret_cast<double*>(base + lay.rowpart_off);
+  double* grampart = reinterpret_cast<double*>(base + lay.grampart_off);
+  const int64_t max_iters = opts->max_iters > 0 ? opts->max_iters : 10 * n;
+  const int64_t max_outer = opts->max_outer > 0 ? opts->max_outer : max_iters;
+  if (opts->record_trace) {
+    const int64_t cap = std::min<int64_t>(max_outer, 1 << 20);
+    if (h->trace_cap < cap) {
+      if (h->d_trace) HIP_OR_FAIL(h, hipFree(h->d_trace));
+      h->d_trace = nullptr;
+      h->trace_cap = 0;
+      if (hipMalloc(&h->d_trace, cap * sizeof(assg_trace_t)) != hipSuccess)
+        return fail(h, ASSG_ERR_ALLOC, "trace allocation failed");
+      h->trace_cap = cap;
+    }
+  }
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  const int nbg = h->gram_blocks[sigma];
+
+  Ctl* c = h->h_ctl;
+  init_ctl(h, c, 0);
+  c->sbar = opts->s_init;
+  c->sbar_next = opts->s_init;
+  c->sigma = sigma;
+  c->growth = opts->growth;
+  c->basis = opts->basis;
+  c->record_trace = opts->record_trace ? 1 : 0;
+  c->trace_cap = opts->record_trace ? h->trace_cap : 0;
+  c->max_outer = max_outer;
+  c->max_iters = max_iters;
+  c->tol = opts->tol;
+
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
+  launch_setup(h->stream, h->d_ctl, Av, h->lpr, b, x, pairs, rowpart);
+  HIP_OR_FAIL(h, hipGetLastError());
+  if (zero_rhs(h, x, n, info, &st)) return st;
+
+  // per-kernel timing: events bracket each matrix-powers launch of a loop
+  const bool timing = opts->time_kernels != 0;
+  struct Timed { int64_t loop; int kind; size_t ev; };   // kind 0: sweep1, 1: sweep>=2, 2: last+gram
+  std::vector<Timed> timed;
+  size_t evn = 0;
+  double t_sweep = 0, t_sweep1 = 0, t_last = 0;
+  int64_t n_sweep = 0, n_sweep1 = 0, n_last = 0;
+
+  int64_t enqueued = 0;
+  int batch = 1;
+  int32_t status = ST_RUNNING;
+  while (true) {
+    timed.clear();
+    evn = 0;
+    for (int bi = 0; bi < batch; ++bi, ++enqueued) {
+      for (int l = 1; l < sigma; ++l) {
+        if (timing) {
+          timed.push_back({enqueued, l == 1 ? 0 : 1, evn});
+          HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
+        }
+        launch_sweep(h->stream, h->d_ctl, l, Av, h->lpr, pairs, lay.ld);
+        if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
+      }
+      if (timing) {
+        timed.push_back({enqueued, 2, evn});
+        HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
+      }
+      launch_last_gram(h->stream, h->d_ctl, sigma, Av, h->lpr, nbg, pairs, plast, lay.ld,
+                       grampart);
+      if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
+      launch_gram_reduce(h->stream, h->d_ctl, sigma, nbg, grampart);
+      launch_controller(h->stream, h->d_ctl, h->d_trace, sigma);
+      launch_recover(h->stream, h->d_ctl, n, pairs, plast, lay.ld, x);
+      launch_check(h->stream, h->d_ctl, h->d_trace, Av, h->lpr, b, x, rowpart, 0);
+    }
+    HIP_OR_FAIL(h, hipGetLastError());
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, 2 * sizeof(int32_t) + sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    status = h->h_status[0];
+    const int64_t kdone = h->h_status[2];   // ctl->k: loops committed so far
+    if (timing) {
+      for (const Timed& tm : timed) {
+        // loops enqueued after the final one exit at once and are not counted;
+        // with f < sigma a sweep past the loop's s-bar also exits at once
+        if (tm.loop >= kdone) continue;
+        float ms = 0.f;
+        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->evpool[tm.ev], h->evpool[tm.ev + 1]));
+        if (tm.kind == 0) { t_sweep1 += ms; ++n_sweep1; }
+        else if (tm.kind == 1) { t_sweep += ms; ++n_sweep; }
+        else { t_last += ms; ++n_last; }
+      }
+    }
+    if (status != ST_RUNNING) break;
+    if (batch < 8) batch *= 2;
+  }
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
+  if (status != ASSG_CONVERGED) {
+    launch_check(h->stream, h->d_ctl, h->d_trace, Av, h->lpr, b, x, rowpart, 1);
+    HIP_OR_FAIL(h, hipGetLastError());
+  }
+  HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+  info->outcome = c->status;
+  info->outer_iters = c->k;
+  info->total_iters = c->m;
+  info->relres_updated = c->relres_upd;
+  info->relres_true = c->relres_true;
+  info->lambda_min_est = c->lmin;
+  info->lambda_max_est = c->lmax;
+  info->c_last = c->c;
+  info->solve_ms = ms;
+  info->sweep_ms = t_sweep;
+  info->sweep_launches = n_sweep;
+  info->sweep1_ms = t_sweep1;
+  info->sweep1_launches = n_sweep1;
+  info->last_gram_ms = t_last;
+  info->last_gram_launches = n_last;
+  info->other_ms = timing ? std::max(0.0, (double)ms - t_sweep - t_sweep1 - t_last) : 0.0;
+  h->trace_count = opts->record_trace ? std::min<int64_t>(c->k, h->trace_cap) : 0;
+  return ASSG_OK;
+}
+
+assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t cap,
+                             int64_t* count) {
+  if (!h || !count || (cap > 0 && !host_buf)) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  *count = h->trace_count;
+  const int64_t nc = std::min(cap, h->trace_count);
+  if (nc > 0) {
+    HIP_OR_FAIL(h, hipMemcpyAsync(host_buf, h->d_trace, nc * sizeof(assg_trace_t),
+                                  hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  }
+  return ASSG_OK;
+}
+
+assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                              double tol, int64_t max_iters, void* workspace,
+                              size_t workspace_bytes, assg_info_t* info) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!b || !x || !info) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  if (!(tol > 0.0 && tol < 1.0) || max_iters < 0)
+    return fail(h, ASSG_ERR_INVALID_ARG, "tol must be in (0,1), max_iters >= 0");
+  assg_status_t st = check_analyzed(h, A);
+  if (st != ASSG_OK) return st;
+  std::memset(info, 0, sizeof(*info));
+  const int64_t n = A->n;
+  char* base = nullptr;
+  WsLayout lay;
+  st = get_workspace(h, n, 1, workspace, workspace_bytes, &base, &lay);
+  if (st != ASSG_OK) return st;
+  double* r = reinterpret_cast<double*>(base);
+  double* p = r + lay.ld;
+  double* w = p + lay.ld;
+  double* rowpart = reinterpret_cast<double*>(base + lay.rowpart_off);
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  Ctl* c = h->h_ctl;
+  init_ctl(h, c, 1);
+  c->tol = tol;
+  c->max_iters = max_iters > 0 ? max_iters : 10 * n;
+  c->max_outer = c->max_iters + 1;
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
+  launch_h_init(h->stream, h->d_ctl, Av, h->lpr, b, x, r, p, rowpart);
+  HIP_OR_FAIL(h, hipGetLastError());
+  if (zero_rhs(h, x, n, info, &st)) return st;
+  int batch = 4;
+  int32_t status = ST_RUNNING;
+  while (true) {
+    for (int bi = 0; bi < batch; ++bi) {
+      launch_h_spmv(h->stream, h->d_ctl, Av, h->lpr, p, w, rowpart);
+      launch_h_update(h->stream, h->d_ctl, n, x, r, p, w, rowpart);
+      launch_h_dir(h->stream, h->d_ctl, n, r, p);
+      launch_check(h->stream, h->d_ctl, nullptr, Av, h->lpr, b, x, rowpart, 0);
+    }
+    HIP_OR_FAIL(h, hipGetLastError());
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    status = h->h_status[0];
+    if (status != ST_RUNNING) break;
+    if (batch < 32) batch *= 2;
+  }
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
+  if (status != ASSG_CONVERGED) {
+    launch_check(h->stream, h->d_ctl, nullptr, Av, h->lpr, b, x, rowpart, 1);
+    HIP_OR_FAIL(h, hipGetLastError());
+  }
+  HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+  info->outcome = c->status;
+  info->outer_iters = c->m;
+  info->total_iters = c->m;
+  info->relres_updated = c->relres_upd;
+  info->relres_true = c->relres_true;
+  info->lambda_min_est = NAN;
+  info->lambda_max_est = NAN;
+  info->c_last = NAN;
+  info->solve_ms = ms;
+  return ASSG_OK;
+}
+
+assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double* p,
+                              const double* r, int32_t s, const double* theta,
+                              const double* gamma, const double* mu, double* Y_out,
+                              double* G_out) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!p || !r || !theta || !gamma || (s > 1 && !mu) || !G_out)
+    return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  if (s < 1 || s > ASSG_MAX_S) return fail(h, ASSG_ERR_INVALID_ARG, "s must be in 1..ASSG_MAX_S");
+  assg_status_t st = check_analyzed(h, A);
+  if (st != ASSG_OK) return st;
+  const int64_t n = A->n;
+  char* base = nullptr;
+  WsLayout lay;
+  st = get_workspace(h, n, s, nullptr, 0, &base, &lay);
+  if (st != ASSG_OK) return st;
+  double2* pairs = reinterpret_cast<double2*>(base + lay.pairs_off);
+  double* plast = reinterpret_cast<double*>(base + lay.plast_off);
+  double* grampart = reinterpret_cast<double*>(base + lay.grampart_off);
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  Ctl* c = h->h_ctl;
+  init_ctl(h, c, 0);
+  c->sbar = s;
+  c->sigma = s;
+  for (int l = 0; l < s; ++l) {
+    c->theta[l] = theta[l];
+    c->gamma[l] = gamma[l];
+    c->mu[l] = (l + 1 < s) ? mu[l] : 0.0;
+  }
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  launch_pair_init(h->stream, n, p, r, pairs);
+  for (int l = 1; l < s; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, h->lpr, pairs, lay.ld);
+  const int nbg = h->gram_blocks[s];
+  launch_last_gram(h->stream, h->d_ctl, s, Av, h->lpr, nbg, pairs, plast, lay.ld, grampart);
+  launch_gram_reduce(h->stream, h->d_ctl, s, nbg, grampart);
+  if (Y_out) launch_export_Y(h->stream, n, s, pairs, plast, lay.ld, Y_out);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  const int nc = 2 * s + 1;
+  for (int a = 0; a < nc; ++a)
+    for (int bb = 0; bb < nc; ++bb) G_out[a * nc + bb] = c->G[a * MAXC + bb];
+  return ASSG_OK;
+}
+
+assg_status_t assg_block_controller(assg_handle_t h, const double* G, int32_t sbar, double nb,
+                                    double tol, int32_t basis, int32_t s_max,
+                                    assg_block_state_t* state, assg_block_result_t* res) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!G || !state || !res) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  if (s_max < 1 || s_max > ASSG_MAX_S || sbar < 1 || sbar > s_max)
+    return fail(h, ASSG_ERR_INVALID_ARG, "need 1 <= sbar <= s_max <= ASSG_MAX_S");
+  if (!(nb > 0.0) || !(tol > 0.0 && tol < 1.0))
+    return fail(h, ASSG_ERR_INVALID_ARG, "need nb > 0 and tol in (0,1)");
+  if (basis != ASSG_BASIS_MONOMIAL && basis != ASSG_BASIS_NEWTON && basis != ASSG_BASIS_CHEBYSHEV)
+    return fail(h, ASSG_ERR_INVALID_ARG, "unknown basis");
+  Ctl* c = h->h_ctl;
+  init_ctl(h, c, 0);
+  const int nc = 2 * sbar + 1;
+  for (int a = 0; a < nc; ++a)
+    for (int bb = 0; bb < nc; ++bb) c->G[a * MAXC + bb] = G[a * nc + bb];
+  c->sbar = sbar;
+  c->sigma = s_max;
+  c->growth = s_max;
+  c->basis = basis;
+  c->tol = tol;
+  c->nb = nb;
+  c->max_iters = INT64_MAX / 2;
+  c->max_outer = INT64_MAX / 2;
+  c->m = state->m;
+  c->c = state->c;
+  c->psi = state->psi;
+  c->alpha_prev = state->alpha_prev;
+  c->beta_prev = state->beta_prev;
+  c->mx_omega = state->mt_max_omega;
+  c->mx_h = state->mt_max_h;
+  c->mx_zeta = state->mt_max_zeta;
+  c->mn_omega = state->mt_min_omega;
+  c->mn_a = state->mt_min_a;
+  c->mn_d = state->mt_min_d;
+  c->mn_g = state->mt_min_g;
+  c->mn_h = state->mt_min_h;
+  c->lmin = state->lmin;
+  c->lmax = state->lmax;
+  for (int l = 0; l < MAXS; ++l) {
+    c->theta[l] = state->theta[l];
+    c->gamma[l] = state->gamma[l];
+    c->mu[l] = state->mu[l];
+  }
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  launch_controller(h->stream, h->d_ctl, nullptr, s_max);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  std::memset(res, 0, sizeof(*res));
+  res->stilde = c->stilde;
+  res->sk = c->sk;
+  res->candidate = c->candidate;
+  res->flags = (c->pending == ASSG_BREAKDOWN ? 1 : 0) | (c->pending == ASSG_DIVERGED ? 2 : 0);
+  res->thr = c->thr;
+  res->rho_m = c->rho_m;
+  res->phi = c->phi;
+  res->relres_updated = c->relres_upd;
+  for (int l = 0; l < MAXS; ++l) {
+    res->kappa[l] = c->kappa[l];
+    res->alpha[l] = c->alphas[l];
+    res->beta[l] = c->betas[l];
+  }
+  for (int i = 0; i < MAXC; ++i) {
+    res->coef_x[i] = c->cx[i];
+    res->coef_r[i] = c->cr[i];
+    res->coef_p[i] = c->cp[i];
+  }
+  state->m = c->m;
+  state->c = c->c;
+  state->psi = c->psi;
+  state->alpha_prev = c->alpha_prev;
+  state->beta_prev = c->beta_prev;
+  state->mt_max_omega = c->mx_omega;
+  state->mt_max_h = c->mx_h;
+  state->mt_max_zeta = c->mx_zeta;
+  state->mt_min_omega = c->mn_omega;
+  state->mt_min_a = c->mn_a;
+  state->mt_min_d = c->mn_d;
+  state->mt_min_g = c->mn_g;
+  state->mt_min_h = c->mn_h;
+  state->lmin = c->lmin;
+  state->lmax = c->lmax;
+  for (int l = 0; l < MAXS; ++l) {
+    state->theta[l] = c->theta[l];
+    state->gamma[l] = c->gamma[l];
+    state->mu[l] = c->mu[l];
+  }
+  return ASSG_OK;
+}
+
+}  // extern "C"
