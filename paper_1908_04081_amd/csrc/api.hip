@@ -32,7 +32,9 @@ struct assg_handle_s {
   // analysis
   int64_t an_n = -1, an_nnz = -1;
   const int32_t* an_rp = nullptr;
-  int lpr = 8;
+  int32_t* d_blk = nullptr;      // row-block partition (row starts, nonzero starts)
+  int32_t* d_blke = nullptr;
+  int32_t nblk = 0;
   int gram_blocks[MAXS + 1] = {0};
   double leja[MAXS];
   std::string err;
@@ -192,6 +194,14 @@ bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_sta
   return true;
 }
 
+// Workgroups of the persistent last-sweep + Gram kernel: the occupancy
+// limit over all CUs, but no more than row blocks (rounded up to 8).
+int gram_grid(assg_handle_t h, int sigma) {
+  const int occ = h->gram_blocks[sigma];
+  const int nb8 = (h->nblk + 7) / 8 * 8;
+  return std::max(8, std::min(occ, nb8));
+}
+
 hipEvent_t pool_event(assg_handle_t h, size_t i) {
   while (h->evpool.size() <= i) {
     hipEvent_t e;
@@ -298,6 +308,8 @@ assg_status_t assg_destroy(assg_handle_t h) {
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_trace) (void)hipFree(h->d_trace);
+  if (h->d_blk) (void)hipFree(h->d_blk);
+  if (h->d_blke) (void)hipFree(h->d_blke);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_status) (void)hipHostFree(h->h_status);
@@ -328,7 +340,22 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
     return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
   for (int64_t i = 0; i < A->n; ++i)
     if (rp[i + 1] < rp[i]) return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr must be nondecreasing");
-  h->lpr = pick_lpr(A->n, A->nnz);
+  std::vector<int32_t> blk, blke;
+  make_blocks(rp.data(), A->n, blk);
+  blke.resize(blk.size());
+  for (size_t i = 0; i < blk.size(); ++i) blke[i] = rp[blk[i]];
+  if (h->d_blk) HIP_OR_FAIL(h, hipFree(h->d_blk));
+  if (h->d_blke) HIP_OR_FAIL(h, hipFree(h->d_blke));
+  h->d_blk = h->d_blke = nullptr;
+  h->an_n = -1;
+  HIP_OR_FAIL(h, hipMalloc(&h->d_blk, blk.size() * sizeof(int32_t)));
+  HIP_OR_FAIL(h, hipMalloc(&h->d_blke, blke.size() * sizeof(int32_t)));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_blk, blk.data(), blk.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_blke, blke.data(), blke.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->nblk = (int32_t)(blk.size() - 1);
   h->an_n = A->n;
   h->an_nnz = A->nnz;
   h->an_rp = A->row_ptr;
@@ -340,10 +367,10 @@ assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, d
   if (!h || !x || !y) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
-  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
-  launch_spmv(h->stream, Av, h->lpr, x, y);
+  launch_spmv(h->stream, Av, x, y);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   return ASSG_OK;
@@ -398,8 +425,8 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
       h->trace_cap = cap;
     }
   }
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
-  const int nbg = h->gram_blocks[sigma];
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  const int nbg = gram_grid(h, sigma);
 
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 0);
@@ -418,7 +445,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
-  launch_setup(h->stream, h->d_ctl, Av, h->lpr, b, x, pairs, rowpart);
+  launch_setup(h->stream, h->d_ctl, Av, b, x, pairs, rowpart);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
 
@@ -442,20 +469,19 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
           timed.push_back({enqueued, l == 1 ? 0 : 1, evn});
           HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
         }
-        launch_sweep(h->stream, h->d_ctl, l, Av, h->lpr, pairs, lay.ld);
+        launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
         if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
       }
       if (timing) {
         timed.push_back({enqueued, 2, evn});
         HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
       }
-      launch_last_gram(h->stream, h->d_ctl, sigma, Av, h->lpr, nbg, pairs, plast, lay.ld,
-                       grampart);
+      launch_last_gram(h->stream, h->d_ctl, sigma, Av, nbg, pairs, plast, lay.ld, grampart);
       if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
       launch_gram_reduce(h->stream, h->d_ctl, sigma, nbg, grampart);
       launch_controller(h->stream, h->d_ctl, h->d_trace, sigma);
       launch_recover(h->stream, h->d_ctl, n, pairs, plast, lay.ld, x);
-      launch_check(h->stream, h->d_ctl, h->d_trace, Av, h->lpr, b, x, rowpart, 0);
+      launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, rowpart, 0);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, 2 * sizeof(int32_t) + sizeof(int32_t),
@@ -480,7 +506,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   }
   HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
   if (status != ASSG_CONVERGED) {
-    launch_check(h->stream, h->d_ctl, h->d_trace, Av, h->lpr, b, x, rowpart, 1);
+    launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, rowpart, 1);
     HIP_OR_FAIL(h, hipGetLastError());
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
@@ -539,7 +565,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   double* p = r + lay.ld;
   double* w = p + lay.ld;
   double* rowpart = reinterpret_cast<double*>(base + lay.rowpart_off);
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 1);
   c->tol = tol;
@@ -549,17 +575,17 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
-  launch_h_init(h->stream, h->d_ctl, Av, h->lpr, b, x, r, p, rowpart);
+  launch_h_init(h->stream, h->d_ctl, Av, b, x, r, p, rowpart);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
   int batch = 4;
   int32_t status = ST_RUNNING;
   while (true) {
     for (int bi = 0; bi < batch; ++bi) {
-      launch_h_spmv(h->stream, h->d_ctl, Av, h->lpr, p, w, rowpart);
+      launch_h_spmv(h->stream, h->d_ctl, Av, p, w, rowpart);
       launch_h_update(h->stream, h->d_ctl, n, x, r, p, w, rowpart);
       launch_h_dir(h->stream, h->d_ctl, n, r, p);
-      launch_check(h->stream, h->d_ctl, nullptr, Av, h->lpr, b, x, rowpart, 0);
+      launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, rowpart, 0);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -571,7 +597,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   }
   HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
   if (status != ASSG_CONVERGED) {
-    launch_check(h->stream, h->d_ctl, nullptr, Av, h->lpr, b, x, rowpart, 1);
+    launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, rowpart, 1);
     HIP_OR_FAIL(h, hipGetLastError());
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
@@ -608,7 +634,7 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   double2* pairs = reinterpret_cast<double2*>(base + lay.pairs_off);
   double* plast = reinterpret_cast<double*>(base + lay.plast_off);
   double* grampart = reinterpret_cast<double*>(base + lay.grampart_off);
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val};
+  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 0);
   c->sbar = s;
@@ -622,9 +648,9 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   launch_pair_init(h->stream, n, p, r, pairs);
-  for (int l = 1; l < s; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, h->lpr, pairs, lay.ld);
-  const int nbg = h->gram_blocks[s];
-  launch_last_gram(h->stream, h->d_ctl, s, Av, h->lpr, nbg, pairs, plast, lay.ld, grampart);
+  for (int l = 1; l < s; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
+  const int nbg = gram_grid(h, s);
+  launch_last_gram(h->stream, h->d_ctl, s, Av, nbg, pairs, plast, lay.ld, grampart);
   launch_gram_reduce(h->stream, h->d_ctl, s, nbg, grampart);
   if (Y_out) launch_export_Y(h->stream, n, s, pairs, plast, lay.ld, Y_out);
   HIP_OR_FAIL(h, hipGetLastError());

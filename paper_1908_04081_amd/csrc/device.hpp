@@ -1,5 +1,5 @@
-// Device-side building blocks for gfx950 (wave64): CSR row products with a
-// group of LPR lanes per row, deterministic reductions, XCD-aware tile maps.
+// Device-side building blocks for gfx950 (wave64): CSR-stream row blocks,
+// deterministic reductions, XCD-aware workgroup maps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,14 +41,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over a group of LPR consecutive lanes (butterfly, fixed order).
-template <int LPR>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
 // Sum of one value per thread over a workgroup of NT threads, deterministic;
 // the result is valid in thread 0.  ``sh`` needs NT/64 doubles.
 template <int NT>
@@ -80,44 +72,103 @@ __device__ __forceinline__ void tile_range(int L, int nb, int64_t ntiles, int64_
   t1 = (ntiles * (L + 1)) / nb;
 }
 
-// ----------------------------------------------------------- CSR rows
-// Lane ``sub`` of a group of LPR lanes accumulates entries sub, sub+LPR, ...
-// of the row; the group then sums with a butterfly.  A's arrays are read
-// with non-temporal loads (streamed once per sweep, no reuse), the source
-// vector through the caches (its entries are reused by neighbouring rows).
-template <int LPR>
-__device__ __forceinline__ double csr_dot(const int32_t* __restrict__ rp,
-                                          const int32_t* __restrict__ ci,
-                                          const double* __restrict__ va,
-                                          const double* __restrict__ x, int64_t row, int sub,
-                                          bool active) {
-  double acc = 0.0;
-  if (active) {
-    const int32_t s = rp[row], e = rp[row + 1];
-    for (int32_t k = s + sub; k < e; k += LPR) acc = fma(ldnt(va + k), x[ldnt(ci + k)], acc);
+// ------------------------------------------------------ CSR-stream rows
+// Source vectors of a product: x[c] (one chain), the pair (x_P[c], x_R[c])
+// (both chains of the matrix powers from one 16-byte gather), or the P part
+// of a pair vector.
+struct Src1 {
+  const double* __restrict__ x;
+  __device__ __forceinline__ double2 get(int32_t c) const { return make_double2(x[c], 0.0); }
+};
+struct Src2 {
+  const double2* __restrict__ x;
+  __device__ __forceinline__ double2 get(int32_t c) const { return x[c]; }
+};
+struct SrcP {
+  const double* __restrict__ x;   // pair vector viewed as doubles
+  __device__ __forceinline__ double2 get(int32_t c) const {
+    return make_double2(x[2 * (int64_t)c], 0.0);
   }
-  return group_sum<LPR>(acc);
+};
+
+// Row sums of one row block (rows r0.., nonzeros [e0, e0+ne)) for NT
+// threads.  When the block fits (ne <= SB_CAP) every thread first issues
+// all of its coalesced value/column loads (indices clamped into the block so
+// the loads are unconditional), then all of its gathers, and stores the
+// products in LDS; after a barrier the owner of each row (thread t, row
+// r0+t) adds its row's products in column order.  Each product is rounded
+// before the sum, as in a sequential CSR product.  A single row longer than
+// SB_CAP is reduced by the whole workgroup (valid in thread 0).
+template <int CH, int NT, int CAP, class S>
+__device__ __forceinline__ void stream_rows(const int32_t* __restrict__ ci,
+                                            const double* __restrict__ va, const S& src,
+                                            int32_t e0, int32_t ne, int32_t rs, int32_t re,
+                                            bool own, double* prod, double* red, double& sx,
+                                            double& sy) {
+  constexpr int K = CAP / NT;
+  const int t = threadIdx.x;
+  sx = 0.0;
+  sy = 0.0;
+  if (ne <= CAP) {
+    if (ne > 0) {
+      double a[K];
+      int32_t c[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int32_t e = t + NT * k;
+        const int32_t ee = e0 + (e < ne ? e : ne - 1);
+        a[k] = ldnt(va + ee);
+        c[k] = ldnt(ci + ee);
+      }
+      double2 v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = src.get(c[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int32_t e = t + NT * k;
+        if (e < ne) {
+          if constexpr (CH == 2) {
+            prod[2 * e] = a[k] * v[k].x;
+            prod[2 * e + 1] = a[k] * v[k].y;
+          } else {
+            prod[e] = a[k] * v[k].x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (own) {
+      for (int32_t e = rs; e < re; ++e) {
+        if constexpr (CH == 2) {
+          const double2 p = reinterpret_cast<const double2*>(prod)[e];
+          sx += p.x;
+          sy += p.y;
+        } else {
+          sx += prod[e];
+        }
+      }
+    }
+  } else {
+    double px = 0.0, py = 0.0;
+    for (int32_t e = t; e < ne; e += NT) {
+      const double a = ldnt(va + e0 + e);
+      const double2 v = src.get(ldnt(ci + e0 + e));
+      px = fma(a, v.x, px);
+      py = fma(a, v.y, py);
+    }
+    px = block_sum<NT>(px, red);
+    if constexpr (CH == 2) py = block_sum<NT>(py, red);
+    sx = px;
+    sy = py;
+  }
 }
 
-// Two right-hand sides stored as pairs: both chains of the matrix powers
-// share each read of A and each 16-byte gather.
-template <int LPR>
-__device__ __forceinline__ double2 csr_dot2(const int32_t* __restrict__ rp,
-                                            const int32_t* __restrict__ ci,
-                                            const double* __restrict__ va,
-                                            const double2* __restrict__ x, int64_t row, int sub,
-                                            bool active) {
-  double ax = 0.0, ay = 0.0;
-  if (active) {
-    const int32_t s = rp[row], e = rp[row + 1];
-    for (int32_t k = s + sub; k < e; k += LPR) {
-      const double a = ldnt(va + k);
-      const double2 v = x[ldnt(ci + k)];
-      ax = fma(a, v.x, ax);
-      ay = fma(a, v.y, ay);
-    }
-  }
-  return make_double2(group_sum<LPR>(ax), group_sum<LPR>(ay));
+// Logical row-block range of this workgroup: [b0, b1) out of nblk, with
+// the XCD-aware logical workgroup id.
+__device__ __forceinline__ void block_range(int32_t nblk, int32_t& b0, int32_t& b1) {
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  b0 = (int32_t)(((int64_t)nblk * L) / gridDim.x);
+  b1 = (int32_t)(((int64_t)nblk * (L + 1)) / gridDim.x);
 }
 
 // ------------------------------------------------ last-block reductions

@@ -50,16 +50,16 @@ struct GramPlanHolder {
   static constexpr int QMAX = (GramPlan<NC, W>::NP + W - 1) / W;
 };
 
-// Per-wave accumulation over one 64-row tile held column-major in LDS
-// (tile[c*64 + lane]); every index is a compile-time constant.
-template <int NC, int W, int WID, int C>
+// Per-wave accumulation over 64 rows of a tile held column-major in LDS
+// (tile[c*TS + row]); every index is a compile-time constant.
+template <int NC, int W, int WID, int TS, int C>
 __device__ __forceinline__ void gram_load_one(double* v, const double* tile, int lane) {
-  if constexpr (GramPlanHolder<NC, W>::P.need[WID][C]) v[C] = tile[C * 64 + lane];
+  if constexpr (GramPlanHolder<NC, W>::P.need[WID][C]) v[C] = tile[C * TS + lane];
 }
-template <int NC, int W, int WID, int... C>
+template <int NC, int W, int WID, int TS, int... C>
 __device__ __forceinline__ void gram_load(double* v, const double* tile, int lane,
                                           std::integer_sequence<int, C...>) {
-  (gram_load_one<NC, W, WID, C>(v, tile, lane), ...);
+  (gram_load_one<NC, W, WID, TS, C>(v, tile, lane), ...);
 }
 template <int NC, int W, int WID, int Q>
 __device__ __forceinline__ void gram_fma_one(double* acc, const double* v) {
@@ -76,10 +76,10 @@ __device__ __forceinline__ void gram_fma(double* acc, const double* v,
   (gram_fma_one<NC, W, WID, Q>(acc, v), ...);
 }
 
-template <int NC, int W, int WID>
+template <int NC, int W, int WID, int TS>
 __device__ __forceinline__ void gram_accum_wave(double* acc, const double* tile, int lane) {
   double v[NC];
-  gram_load<NC, W, WID>(v, tile, lane, std::make_integer_sequence<int, NC>{});
+  gram_load<NC, W, WID, TS>(v, tile, lane, std::make_integer_sequence<int, NC>{});
   gram_fma<NC, W, WID>(acc, v, std::make_integer_sequence<int, GramPlanHolder<NC, W>::QMAX>{});
 }
 

@@ -1,6 +1,6 @@
 // Row kernels of the adaptive s-step CG hot path for gfx950 (wave64).
 //
-//  k_spmv        y = A x                                   (CSR, LPR lanes/row)
+//  k_spmv        y = A x                                   (CSR-stream row blocks)
 //  k_setup       r0 = b - A x0, Y level 0 = (r0, r0), ||b||  (Algorithm 5 start)
 //  k_sweep       one matrix-powers level of both chains (2.3) from one read of A
 //  k_last_gram   last P-chain level fused with the Gram partial sums of G = Y^T Y
@@ -21,16 +21,6 @@
 
 namespace assg {
 
-#define ASSG_LPR_SWITCH(lpr, CALL) \
-  switch (lpr) {                   \
-    case 2: { constexpr int LPR = 2; CALL; } break;   \
-    case 4: { constexpr int LPR = 4; CALL; } break;   \
-    case 8: { constexpr int LPR = 8; CALL; } break;   \
-    case 16: { constexpr int LPR = 16; CALL; } break; \
-    case 32: { constexpr int LPR = 32; CALL; } break; \
-    default: { constexpr int LPR = 64; CALL; } break; \
-  }
-
 int row_blocks(int64_t n) {
   const int64_t ntiles = (n + TILE_ROWS - 1) / TILE_ROWS;
   int64_t nb = ((ntiles + NXCD - 1) / NXCD) * NXCD;
@@ -39,12 +29,48 @@ int row_blocks(int64_t n) {
   return (int)nb;
 }
 
-int pick_lpr(int64_t n, int64_t nnz) {
-  const int64_t avg = (nnz + n - 1) / (n > 0 ? n : 1);
-  int l = 2;
-  while (l < 64 && l < avg) l <<= 1;
-  return l;
+void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk) {
+  blk.clear();
+  blk.push_back(0);
+  int64_t r = 0;
+  while (r < n) {
+    const int64_t r0 = r;
+    ++r;                                    // a block always takes its first row
+    if ((int64_t)rp[r] - rp[r0] <= SB_CAP)
+      while (r < n && r - r0 < SB_ROWS && (int64_t)rp[r + 1] - rp[r0] <= SB_CAP) ++r;
+    blk.push_back((int32_t)r);
+  }
 }
+
+// Grid of a row-block kernel: one workgroup per block (rounded up to a
+// multiple of 8), or at most ``cap`` workgroups each looping over a
+// contiguous range of blocks.
+static int block_grid(const CsrView& A, int cap) {
+  int64_t g = ((int64_t)A.nblk + NXCD - 1) / NXCD * NXCD;
+  if (g > cap) g = cap;
+  if (g < NXCD) g = NXCD;
+  return (int)g;
+}
+
+// Bounds of row block b and of the calling thread's own row.
+struct BlockRows {
+  int32_t r0, nr, e0, ne, rs, re;
+  bool own;
+  int64_t row;
+  __device__ __forceinline__ BlockRows(const CsrView& A, int32_t b) {
+    r0 = A.blk[b];
+    nr = A.blk[b + 1] - r0;
+    e0 = A.blke[b];
+    ne = A.blke[b + 1] - e0;
+    own = (int)threadIdx.x < nr;
+    row = (int64_t)r0 + threadIdx.x;
+    rs = re = 0;
+    if (own) {
+      rs = A.rp[row] - e0;
+      re = A.rp[row + 1] - e0;
+    }
+  }
+};
 
 // Rows owned by this workgroup: tiles [t0, t1) of TILE_ROWS rows.
 struct RowIter {
@@ -56,184 +82,201 @@ struct RowIter {
 };
 
 // ------------------------------------------------------------------ SpMV
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_spmv(CsrView A, const double* __restrict__ x,
-                                                      double* __restrict__ y) {
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int r = 0; r < TILE_ROWS; r += RPP) {
-      const int64_t row = t * TILE_ROWS + r + g;
-      const bool act = row < A.n;
-      const double v = csr_dot<LPR>(A.rp, A.ci, A.va, x, row, sub, act);
-      if (act && sub == 0) y[row] = v;
-    }
+__global__ __launch_bounds__(256) void k_spmv(CsrView A, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[4];
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t b = b0; b < b1; ++b) {
+    const BlockRows br(A, b);
+    double sx, sy;
+    stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{x}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, sx, sy);
+    if (br.own) y[br.row] = sx;
+    __syncthreads();
+  }
 }
 
-void launch_spmv(hipStream_t s, const CsrView& A, int lpr, const double* x, double* y) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_spmv<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, A, x, y));
+void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y) {
+  hipLaunchKernelGGL(k_spmv, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, A, x, y);
 }
 
 // ----------------------------------------------------------------- setup
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_setup(Ctl* ctl, CsrView A,
-                                                       const double* __restrict__ b,
-                                                       const double* __restrict__ x,
-                                                       double2* __restrict__ pairs,
-                                                       double* __restrict__ partials) {
-  __shared__ double sh[ROW_THREADS / WAVE];
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+__global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CsrView A, const double* __restrict__ b,
+                                               const double* __restrict__ x,
+                                               double2* __restrict__ pairs,
+                                               double* __restrict__ partials) {
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[4];
   double part = 0.0;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int r = 0; r < TILE_ROWS; r += RPP) {
-      const int64_t row = t * TILE_ROWS + r + g;
-      const bool act = row < A.n;
-      const double ax = csr_dot<LPR>(A.rp, A.ci, A.va, x, row, sub, act);
-      if (act && sub == 0) {
-        const double bi = b[row];
-        const double ri = bi - ax;
-        pairs[row] = make_double2(ri, ri);
-        part = fma(bi, bi, part);
-      }
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t bb = b0; bb < b1; ++bb) {
+    const BlockRows br(A, bb);
+    double bi = 0.0;
+    if (br.own) bi = b[br.row];
+    double ax, unused;
+    stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{x}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, ax, unused);
+    if (br.own) {
+      const double ri = bi - ax;
+      pairs[br.row] = make_double2(ri, ri);
+      part = fma(bi, bi, part);
     }
-  part = block_sum<ROW_THREADS>(part, sh);
+    __syncthreads();
+  }
+  part = block_sum<256>(part, red);
   double tot;
-  if (last_block_total(part, partials, ctl, &tot, sh)) ctl->nb = sqrt(tot);
+  if (last_block_total(part, partials, ctl, &tot, red)) ctl->nb = sqrt(tot);
 }
 
-void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* b,
-                  const double* x, double2* pairs, double* partials) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_setup<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, ctl,
-                                          A, b, x, pairs, partials));
+void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
+                  double2* pairs, double* partials) {
+  hipLaunchKernelGGL(k_setup, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, b,
+                     x, pairs, partials);
 }
 
 // ------------------------------------------------ matrix powers: one level
 // y_l = (A y_{l-1} - theta_{l-1} y_{l-1} - mu_{l-2} y_{l-2}) / gamma_{l-1}
-// for both chains (2.3); levels beyond the loop's s-bar exit at once.
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_sweep(const Ctl* __restrict__ ctl, int level,
-                                                       CsrView A, double2* __restrict__ pairs,
-                                                       int64_t ld) {
+// for both chains (2.3) from one read of A and one 16-byte gather per
+// nonzero; levels beyond the loop's s-bar exit at once.
+__global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctl, int level, CsrView A,
+                                               double2* __restrict__ pairs, int64_t ld) {
   if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
+  __shared__ double prod[2 * SB_CAP];
+  __shared__ double red[4];
   const double th = ctl->theta[level - 1];
   const double ga = ctl->gamma[level - 1];
   const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
   const double2* __restrict__ X = pairs + (size_t)(level - 1) * ld;
   const double2* __restrict__ X2 = pairs + (size_t)(level >= 2 ? level - 2 : 0) * ld;
   double2* __restrict__ Yo = pairs + (size_t)level * ld;
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int r = 0; r < TILE_ROWS; r += RPP) {
-      const int64_t row = t * TILE_ROWS + r + g;
-      const bool act = row < A.n;
-      const double2 a = csr_dot2<LPR>(A.rp, A.ci, A.va, X, row, sub, act);
-      if (act && sub == 0) {
-        const double2 xo = X[row];
-        double yx = a.x - th * xo.x;
-        double yy = a.y - th * xo.y;
-        if (mu != 0.0) {
-          const double2 x2 = X2[row];
-          yx -= mu * x2.x;
-          yy -= mu * x2.y;
-        }
-        Yo[row] = make_double2(yx / ga, yy / ga);
-      }
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t b = b0; b < b1; ++b) {
+    const BlockRows br(A, b);
+    double2 xo = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
+    if (br.own) {
+      xo = X[br.row];
+      if (mu != 0.0) x2 = X2[br.row];
     }
+    double ax, ay;
+    stream_rows<2, 256, SB_CAP>(A.ci, A.va, Src2{X}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, ax, ay);
+    if (br.own) {
+      double yx = ax - th * xo.x;
+      double yy = ay - th * xo.y;
+      if (mu != 0.0) {
+        yx -= mu * x2.x;
+        yy -= mu * x2.y;
+      }
+      Yo[br.row] = make_double2(yx / ga, yy / ga);
+    }
+    __syncthreads();
+  }
 }
 
-void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, int lpr,
-                  double2* pairs, int64_t ld) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_sweep<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, ctl,
-                                          level, A, pairs, ld));
+void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, double2* pairs,
+                  int64_t ld) {
+  hipLaunchKernelGGL(k_sweep, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, ctl, level, A,
+                     pairs, ld);
 }
 
 // --------------------------------- last level fused with the Gram partials
-// For each 64-row tile: stage Y's 2 sbar columns in LDS (column-major),
-// compute P_sbar for the tile (its theta/mu terms read the staged columns),
-// then every wave adds its share of the unique products Y_a * Y_b to
-// register accumulators.  Columns past 2 sbar + 1 stay zero.
+// For each row block (<= 256 rows): stage Y's 2 sbar columns in LDS
+// (column-major, 256-row stride, rows past the block zero), compute P_sbar
+// for the block (CSR-stream; its theta/mu terms read the staged columns),
+// then every wave adds its share of the unique products Y_a * Y_b of the
+// block's rows to register accumulators.  Columns past 2 sbar + 1 stay zero.
 template <int NC, int W>
 __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctl, CsrView A,
-                                                      int lpr, const double2* __restrict__ pairs,
+                                                      const double2* __restrict__ pairs,
                                                       double* __restrict__ plast, int64_t ld,
                                                       double* __restrict__ partials) {
   if (ctl->status != ST_RUNNING) return;
   constexpr int NT = 64 * W;
   constexpr int QMAX = GramPlanHolder<NC, W>::QMAX;
-  __shared__ double tile[NC * 64];
+  constexpr int TS = SB_ROWS;
+  __shared__ double tile[NC * TS];
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[W];
   const int s = ctl->sbar;
   const double th = ctl->theta[s - 1];
   const double ga = ctl->gamma[s - 1];
   const double mu = (s >= 2) ? ctl->mu[s - 2] : 0.0;
   const double* __restrict__ xsrc = reinterpret_cast<const double*>(pairs + (size_t)(s - 1) * ld);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < (NC - 2 * s - 1) * 64; i += NT) tile[(2 * s + 1) * 64 + i] = 0.0;
+  for (int i = tid; i < (NC - 2 * s - 1) * TS; i += NT) tile[(2 * s + 1) * TS + i] = 0.0;
   double acc[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) acc[q] = 0.0;
 
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
-  int64_t t0, t1;
-  tile_range(L, gridDim.x, (A.n + 63) / 64, t0, t1);
-  const int rpp = NT / lpr;
-  const int g = tid / lpr, sub = tid % lpr;
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t base = t * 64;
-    for (int i = tid; i < s * 64; i += NT) {
-      const int l = i >> 6, rl = i & 63;
-      const int64_t row = base + rl;
-      double2 v = make_double2(0.0, 0.0);
-      if (row < A.n) v = pairs[(size_t)l * ld + row];
-      tile[(2 * l) * 64 + rl] = v.x;
-      tile[(2 * l + 1) * 64 + rl] = v.y;
+  // Basis rows of the next block are loaded into registers while the Gram
+  // products of the current block run (software pipelining), where the
+  // register budget allows it (up to 21 columns); otherwise per block.
+  constexpr bool PREFETCH = NC <= 21;
+  constexpr int PF = ((NC - 1) / 2 * TS + NT - 1) / NT;
+  double2 pf[PF];
+  auto load_pairs = [&](int32_t b) {
+    const int32_t r0 = A.blk[b], nr = A.blk[b + 1] - r0;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = tid + NT * k;
+      const int l = i / TS, rl = i % TS;
+      pf[k] = (l < s && rl < nr) ? pairs[(size_t)l * ld + r0 + rl] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    for (int r = 0; r < 64; r += rpp) {
-      const int rl = r + g;
-      const int64_t row = base + rl;
-      const bool act = (rl < 64) && (row < A.n);
-      double a = 0.0;
-      if (act) {
-        const int32_t e0 = A.rp[row], e1 = A.rp[row + 1];
-        for (int32_t k = e0 + sub; k < e1; k += lpr)
-          a = fma(ldnt(A.va + k), xsrc[2 * (int64_t)ldnt(A.ci + k)], a);
-      }
-      for (int off = lpr >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-      if (sub == 0 && rl < 64) {
-        double y = 0.0;
-        if (act) {
-          y = a - th * tile[(2 * s - 2) * 64 + rl];
-          if (mu != 0.0) y -= mu * tile[(2 * s - 4) * 64 + rl];
-          y = y / ga;
-          plast[row] = y;
-        }
-        tile[(2 * s) * 64 + rl] = y;
+  };
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  if (PREFETCH && b0 < b1) load_pairs(b0);
+  for (int32_t b = b0; b < b1; ++b) {
+    if (!PREFETCH) load_pairs(b);
+    const BlockRows br(A, b);
+    // stage the 2 s basis columns of the block's rows (zero past the block)
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = tid + NT * k;
+      const int l = i / TS, rl = i % TS;
+      if (l < s) {
+        tile[(2 * l) * TS + rl] = pf[k].x;
+        tile[(2 * l + 1) * TS + rl] = pf[k].y;
       }
     }
+    double a, unused;
+    stream_rows<1, NT, SB_CAP>(A.ci, A.va, SrcP{xsrc}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                               red, a, unused);
+    if (tid < TS) {
+      double y = 0.0;
+      if (br.own) {
+        y = a - th * tile[(2 * s - 2) * TS + tid];
+        if (mu != 0.0) y -= mu * tile[(2 * s - 4) * TS + tid];
+        y = y / ga;
+        plast[br.row] = y;
+      }
+      tile[(2 * s) * TS + tid] = y;
+    }
     __syncthreads();
-    switch (wave) {
-      case 0: gram_accum_wave<NC, W, 0>(acc, tile, lane); break;
-      case 1: gram_accum_wave<NC, W, 1>(acc, tile, lane); break;
-      case 2: gram_accum_wave<NC, W, 2>(acc, tile, lane); break;
-      case 3: gram_accum_wave<NC, W, 3>(acc, tile, lane); break;
-      default:
-        if constexpr (W > 4) {
-          switch (wave) {
-            case 4: gram_accum_wave<NC, W, (W > 4 ? 4 : 0)>(acc, tile, lane); break;
-            case 5: gram_accum_wave<NC, W, (W > 5 ? 5 : 0)>(acc, tile, lane); break;
-            case 6: gram_accum_wave<NC, W, (W > 6 ? 6 : 0)>(acc, tile, lane); break;
-            case 7: gram_accum_wave<NC, W, (W > 7 ? 7 : 0)>(acc, tile, lane); break;
+    if (PREFETCH && b + 1 < b1) load_pairs(b + 1);
+    const int nsub = (br.nr + 63) >> 6;
+    for (int q = 0; q < nsub; ++q) {
+      const double* tq = tile + q * 64;
+      switch (wave) {
+        case 0: gram_accum_wave<NC, W, 0, TS>(acc, tq, lane); break;
+        case 1: gram_accum_wave<NC, W, 1, TS>(acc, tq, lane); break;
+        case 2: gram_accum_wave<NC, W, 2, TS>(acc, tq, lane); break;
+        case 3: gram_accum_wave<NC, W, 3, TS>(acc, tq, lane); break;
+        default:
+          if constexpr (W > 4) {
+            switch (wave) {
+              case 4: gram_accum_wave<NC, W, (W > 4 ? 4 : 0), TS>(acc, tq, lane); break;
+              case 5: gram_accum_wave<NC, W, (W > 5 ? 5 : 0), TS>(acc, tq, lane); break;
+              case 6: gram_accum_wave<NC, W, (W > 6 ? 6 : 0), TS>(acc, tq, lane); break;
+              case 7: gram_accum_wave<NC, W, (W > 7 ? 7 : 0), TS>(acc, tq, lane); break;
+            }
           }
-        }
-        break;
+          break;
+      }
     }
     __syncthreads();
   }
@@ -298,13 +341,12 @@ int last_gram_blocks(int sigma, int cus) {
   return nb;
 }
 
-void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int lpr,
-                      int nblocks, const double2* pairs, double* plast, int64_t ld,
-                      double* partials) {
+void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int nblocks,
+                      const double2* pairs, double* plast, int64_t ld, double* partials) {
   ASSG_SIGMA_SWITCH(sigma, {
     constexpr int W = gram_waves<NC>();
-    hipLaunchKernelGGL((k_last_gram<NC, W>), dim3(nblocks), dim3(64 * W), 0, s, ctl, A, lpr,
-                       pairs, plast, ld, partials);
+    hipLaunchKernelGGL((k_last_gram<NC, W>), dim3(nblocks), dim3(64 * W), 0, s, ctl, A, pairs,
+                       plast, ld, partials);
   });
 }
 
@@ -409,13 +451,12 @@ __device__ void commit_loop(Ctl* ctl, assg_trace_t* trace, bool checked, double 
   ctl->status = st;
 }
 
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_check(Ctl* ctl, assg_trace_t* trace, CsrView A,
-                                                       const double* __restrict__ b,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ partials,
-                                                       int measure_only) {
-  __shared__ double sh[ROW_THREADS / WAVE];
+__global__ __launch_bounds__(256) void k_check(Ctl* ctl, assg_trace_t* trace, CsrView A,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ x,
+                                               double* __restrict__ partials, int measure_only) {
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[4];
   if (!measure_only) {
     if (ctl->status != ST_RUNNING) return;
     if (!ctl->candidate) {
@@ -423,23 +464,25 @@ __global__ __launch_bounds__(ROW_THREADS) void k_check(Ctl* ctl, assg_trace_t* t
       return;
     }
   }
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
   double part = 0.0;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int r = 0; r < TILE_ROWS; r += RPP) {
-      const int64_t row = t * TILE_ROWS + r + g;
-      const bool act = row < A.n;
-      const double ax = csr_dot<LPR>(A.rp, A.ci, A.va, x, row, sub, act);
-      if (act && sub == 0) {
-        const double ri = b[row] - ax;
-        part = fma(ri, ri, part);
-      }
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t bb = b0; bb < b1; ++bb) {
+    const BlockRows br(A, bb);
+    double bi = 0.0;
+    if (br.own) bi = b[br.row];
+    double ax, unused;
+    stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{x}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, ax, unused);
+    if (br.own) {
+      const double ri = bi - ax;
+      part = fma(ri, ri, part);
     }
-  part = block_sum<ROW_THREADS>(part, sh);
+    __syncthreads();
+  }
+  part = block_sum<256>(part, red);
   double tot;
-  if (last_block_total(part, partials, ctl, &tot, sh)) {
+  if (last_block_total(part, partials, ctl, &tot, red)) {
     const double rel = sqrt(tot) / ctl->nb;
     if (measure_only)
       ctl->relres_true = rel;
@@ -448,46 +491,44 @@ __global__ __launch_bounds__(ROW_THREADS) void k_check(Ctl* ctl, assg_trace_t* t
   }
 }
 
-void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A, int lpr,
+void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A,
                   const double* b, const double* x, double* partials, int measure_only) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_check<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, ctl,
-                                          trace, A, b, x, partials, measure_only));
+  hipLaunchKernelGGL(k_check, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, trace,
+                     A, b, x, partials, measure_only);
 }
 
 // ------------------------------------------------------------------ HSCG
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_h_init(Ctl* ctl, CsrView A,
-                                                        const double* __restrict__ b,
-                                                        const double* __restrict__ x,
-                                                        double* __restrict__ r,
-                                                        double* __restrict__ p,
-                                                        double* __restrict__ partials) {
-  __shared__ double sh[ROW_THREADS / WAVE];
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+__global__ __launch_bounds__(256) void k_h_init(Ctl* ctl, CsrView A, const double* __restrict__ b,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ r, double* __restrict__ p,
+                                                double* __restrict__ partials) {
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[4];
   double pb = 0.0, pr = 0.0;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int rr = 0; rr < TILE_ROWS; rr += RPP) {
-      const int64_t row = t * TILE_ROWS + rr + g;
-      const bool act = row < A.n;
-      const double ax = csr_dot<LPR>(A.rp, A.ci, A.va, x, row, sub, act);
-      if (act && sub == 0) {
-        const double bi = b[row];
-        const double ri = bi - ax;
-        r[row] = ri;
-        p[row] = ri;
-        pb = fma(bi, bi, pb);
-        pr = fma(ri, ri, pr);
-      }
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t bb = b0; bb < b1; ++bb) {
+    const BlockRows br(A, bb);
+    double bi = 0.0;
+    if (br.own) bi = b[br.row];
+    double ax, unused;
+    stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{x}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, ax, unused);
+    if (br.own) {
+      const double ri = bi - ax;
+      r[br.row] = ri;
+      p[br.row] = ri;
+      pb = fma(bi, bi, pb);
+      pr = fma(ri, ri, pr);
     }
+    __syncthreads();
+  }
   // two sums: partials[0..nb) and partials[nb..2nb)
-  pb = block_sum<ROW_THREADS>(pb, sh);
-  pr = block_sum<ROW_THREADS>(pr, sh);
+  pb = block_sum<256>(pb, red);
+  pr = block_sum<256>(pr, red);
   double tot;
   if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = pr;
-  if (last_block_total(pb, partials, ctl, &tot, sh)) {
+  if (last_block_total(pb, partials, ctl, &tot, red)) {
     double rr = 0.0;
     for (int i = 0; i < (int)gridDim.x; ++i)
       rr += __hip_atomic_load(partials + gridDim.x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -496,38 +537,38 @@ __global__ __launch_bounds__(ROW_THREADS) void k_h_init(Ctl* ctl, CsrView A,
   }
 }
 
-void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* b,
-                   const double* x, double* r, double* p, double* partials) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_h_init<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, ctl,
-                                          A, b, x, r, p, partials));
+void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
+                   double* r, double* p, double* partials) {
+  hipLaunchKernelGGL(k_h_init, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, b,
+                     x, r, p, partials);
 }
 
 // w = A p with the p^T w partial sum; the last workgroup forms alpha.
-template <int LPR>
-__global__ __launch_bounds__(ROW_THREADS) void k_h_spmv(Ctl* ctl, CsrView A,
-                                                        const double* __restrict__ p,
-                                                        double* __restrict__ w,
-                                                        double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_h_spmv(Ctl* ctl, CsrView A, const double* __restrict__ p,
+                                                double* __restrict__ w,
+                                                double* __restrict__ partials) {
   if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
-  __shared__ double sh[ROW_THREADS / WAVE];
-  constexpr int RPP = ROW_THREADS / LPR;
-  const int g = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+  __shared__ double prod[SB_CAP];
+  __shared__ double red[4];
   double part = 0.0;
-  RowIter it(A.n);
-  for (int64_t t = it.t0; t < it.t1; ++t)
-    for (int r = 0; r < TILE_ROWS; r += RPP) {
-      const int64_t row = t * TILE_ROWS + r + g;
-      const bool act = row < A.n;
-      const double v = csr_dot<LPR>(A.rp, A.ci, A.va, p, row, sub, act);
-      if (act && sub == 0) {
-        w[row] = v;
-        part = fma(p[row], v, part);
-      }
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t bb = b0; bb < b1; ++bb) {
+    const BlockRows br(A, bb);
+    double pi = 0.0;
+    if (br.own) pi = p[br.row];
+    double v, unused;
+    stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{p}, br.e0, br.ne, br.rs, br.re, br.own, prod,
+                                red, v, unused);
+    if (br.own) {
+      w[br.row] = v;
+      part = fma(pi, v, part);
     }
-  part = block_sum<ROW_THREADS>(part, sh);
+    __syncthreads();
+  }
+  part = block_sum<256>(part, red);
   double pw;
-  if (last_block_total(part, partials, ctl, &pw, sh)) {
+  if (last_block_total(part, partials, ctl, &pw, red)) {
     if (!(pw > 0.0) || !isfinite(pw)) {
       ctl->pending = isfinite(pw) ? ASSG_BREAKDOWN : ASSG_DIVERGED;
     } else {
@@ -536,11 +577,10 @@ __global__ __launch_bounds__(ROW_THREADS) void k_h_spmv(Ctl* ctl, CsrView A,
   }
 }
 
-void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* p,
-                   double* w, double* partials) {
-  const int nb = row_blocks(A.n);
-  ASSG_LPR_SWITCH(lpr, hipLaunchKernelGGL(k_h_spmv<LPR>, dim3(nb), dim3(ROW_THREADS), 0, s, ctl,
-                                          A, p, w, partials));
+void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, const double* p, double* w,
+                   double* partials) {
+  hipLaunchKernelGGL(k_h_spmv, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, p,
+                     w, partials);
 }
 
 // x += alpha p; r -= alpha w; r^T r partial; the last workgroup forms beta

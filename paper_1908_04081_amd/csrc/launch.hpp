@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "assg.h"
 #include "ctl.hpp"
 
@@ -13,36 +15,44 @@ constexpr int TILE_ROWS = 256;     // rows per tile of the row kernels
 constexpr int ROW_THREADS = 256;   // threads per workgroup of the row kernels
 constexpr int MAX_ROW_BLOCKS = 2048;
 
+// Row blocks of the CSR-stream kernels: at most SB_ROWS rows and SB_CAP
+// nonzeros each, except single rows longer than SB_CAP.
+constexpr int SB_ROWS = 256;
+constexpr int SB_CAP = 2048;
+
 struct CsrView {
   int64_t n, nnz;
   const int32_t* rp;
   const int32_t* ci;
   const double* va;
+  const int32_t* blk;   // nblk + 1 row starts of the row blocks
+  const int32_t* blke;  // nblk + 1 nonzero starts (row_ptr[blk[b]])
+  int32_t nblk;
 };
 
-// Launch shape of the row kernels for n rows: a multiple of 8 workgroups
-// (XCD-aware mapping), at most MAX_ROW_BLOCKS, each owning a contiguous
-// range of 256-row tiles.
+// Greedy row-block partition (host): rows are appended while a block has
+// fewer than SB_ROWS rows and at most SB_CAP nonzeros.
+void make_blocks(const int32_t* row_ptr, int64_t n, std::vector<int32_t>& blk);
+
+// Launch shape of the streaming row kernels for n rows: a multiple of 8
+// workgroups (XCD-aware mapping), at most MAX_ROW_BLOCKS, each owning a
+// contiguous range of 256-row tiles.
 int row_blocks(int64_t n);
 
-// Lanes per row of the CSR kernels: power of two in [2, 64].
-int pick_lpr(int64_t n, int64_t nnz);
-
-void launch_spmv(hipStream_t s, const CsrView& A, int lpr, const double* x, double* y);
+void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
 
 // r = b - A x, pairs[0] = (r, r), ctl->nb = ||b||.
-void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* b,
-                  const double* x, double2* pairs, double* partials);
+void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
+                  double2* pairs, double* partials);
 
 // Two-chain sweep producing basis level ``level`` (1 <= level < sbar).
-void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, int lpr,
-                  double2* pairs, int64_t ld);
+void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, double2* pairs,
+                  int64_t ld);
 
 // Last sweep (P chain, level sbar) fused with the Gram partial sums.
 int last_gram_blocks(int sigma, int cus);
-void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int lpr,
-                      int nblocks, const double2* pairs, double* plast, int64_t ld,
-                      double* partials);
+void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int nblocks,
+                      const double2* pairs, double* plast, int64_t ld, double* partials);
 void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const double* partials);
 
 void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma);
@@ -53,14 +63,14 @@ void launch_recover(hipStream_t s, const Ctl* ctl, int64_t n, double2* pairs,
 // True relative residual when the loop's updated residual reached tol, then
 // commit of the loop's outcome.  With ``measure_only`` it only stores
 // ||b - A x|| / ||b|| in ctl->relres_true.
-void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A, int lpr,
+void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A,
                   const double* b, const double* x, double* partials, int measure_only);
 
 // HSCG (Algorithm 1).
-void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* b,
-                   const double* x, double* r, double* p, double* partials);
-void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, int lpr, const double* p,
-                   double* w, double* partials);
+void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
+                   double* r, double* p, double* partials);
+void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, const double* p, double* w,
+                   double* partials);
 void launch_h_update(hipStream_t s, Ctl* ctl, int64_t n, double* x, double* r, const double* p,
                      const double* w, double* partials);
 void launch_h_dir(hipStream_t s, const Ctl* ctl, int64_t n, const double* r, double* p);

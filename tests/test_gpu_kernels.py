@@ -45,7 +45,22 @@ def _ragged_spd(n=3001, seed=7):
     return P.diag_scale(M)
 
 
+def _arrow_spd(n=6000):
+    """Arrow matrix: row/column 0 dense (a row longer than a workgroup's
+    nonzero block), unit-diagonal-dominant otherwise."""
+    rows = np.concatenate([np.zeros(n - 1, dtype=np.int64), np.arange(1, n), np.arange(n)])
+    cols = np.concatenate([np.arange(1, n), np.zeros(n - 1, dtype=np.int64), np.arange(n)])
+    vals = np.concatenate([np.full(n - 1, -0.5 / n), np.full(n - 1, -0.5 / n),
+                           np.linspace(1.0, 2.0, n)])
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    M.sort_indices()
+    M.indices = M.indices.astype(np.int32)
+    M.indptr = M.indptr.astype(np.int32)
+    return M
+
+
 PROBLEMS = {
+    "arrow_6000": lambda: _arrow_spd(6000),
     "poisson2d_64": lambda: P.poisson2d(64),
     "poisson2d_37": lambda: P.poisson2d(37),
     "poisson3d_21": lambda: P.poisson3d(21),
@@ -76,7 +91,22 @@ def test_spmv_matches_scipy(env, name):
     assert np.all(err <= 1e-14 * scale + 1e-300), float((err / (scale + 1e-300)).max())
 
 
-@pytest.mark.parametrize("name", ["poisson2d_37", "poisson3d_21", "diffusion27_13", "ragged_3001"])
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_spmv_bitwise_in_row_order(env, name):
+    """Rows of at most 2048 nonzeros are summed product by product in column
+    order, which is scipy's sequential CSR product: bit-identical results."""
+    torch, L, h = env
+    A = PROBLEMS[name]()
+    Ad = _dev(torch, L, h, A)
+    x = np.random.default_rng(2).standard_normal(A.shape[0])
+    y = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    L.assg_spmv(h, Ad, torch.from_numpy(x).cuda(), y)
+    short = np.diff(A.indptr) <= 2048
+    assert np.array_equal(y.cpu().numpy()[short], (A @ x)[short])
+
+
+@pytest.mark.parametrize("name", ["poisson2d_37", "poisson3d_21", "diffusion27_13", "ragged_3001",
+                                  "arrow_6000"])
 @pytest.mark.parametrize("basis", ["monomial", "newton", "chebyshev"])
 @pytest.mark.parametrize("s", [1, 3, 10, 16])
 def test_basis_and_gram_match_oracle(env, name, basis, s):
