@@ -35,6 +35,7 @@ struct assg_handle_s {
   int32_t* d_blk = nullptr;      // row-block partition (row starts, nonzero starts)
   int32_t* d_blke = nullptr;
   int32_t nblk = 0;
+  double* d_part = nullptr;      // per-workgroup partial sums (sized at analyze)
   int gram_blocks[MAXS + 1] = {0};
   double leja[MAXS];
   std::string err;
@@ -82,20 +83,21 @@ void leja_table(double* t, int count) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Workspace: the basis (s_max pair vectors + P_s; for HSCG r, two p
+// buffers and w in the same region) and the Gram partials.
 struct WsLayout {
   int64_t ld;
-  size_t pairs_off, plast_off, rowpart_off, grampart_off, total;
+  size_t pairs_off, plast_off, grampart_off, total;
 };
 
 WsLayout ws_layout(int64_t n, int32_t s_max) {
   WsLayout w;
   w.ld = (int64_t)align_up((size_t)n, 32);
   const size_t vec = (size_t)w.ld * sizeof(double);
-  const size_t basis = std::max((size_t)s_max * 2 * vec + vec, 3 * vec);
+  const size_t basis = std::max((size_t)s_max * 2 * vec + vec, 4 * vec);
   w.pairs_off = 0;
   w.plast_off = (size_t)s_max * 2 * vec;
-  w.rowpart_off = align_up(basis, 256);
-  w.grampart_off = w.rowpart_off + align_up(2 * MAX_ROW_BLOCKS * sizeof(double), 256);
+  w.grampart_off = align_up(basis, 256);
   const size_t np = (size_t)(2 * s_max + 1) * (2 * s_max + 2) / 2;
   w.total = w.grampart_off + align_up(np * 4096 * sizeof(double), 256);
   return w;
@@ -310,6 +312,7 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_trace) (void)hipFree(h->d_trace);
   if (h->d_blk) (void)hipFree(h->d_blk);
   if (h->d_blke) (void)hipFree(h->d_blke);
+  if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_status) (void)hipHostFree(h->h_status);
@@ -354,8 +357,10 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
                                 hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_blke, blke.data(), blke.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, h->stream));
-  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   h->nblk = (int32_t)(blk.size() - 1);
+  if (h->d_part) HIP_OR_FAIL(h, hipFree(h->d_part));
+  h->d_part = nullptr;
+  HIP_OR_FAIL(h, hipMalloc(&h->d_part, reduce_doubles(h->nblk) * sizeof(double)));
   h->an_n = A->n;
   h->an_nnz = A->nnz;
   h->an_rp = A->row_ptr;
@@ -410,7 +415,6 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   if (st != ASSG_OK) return st;
   double2* pairs = reinterpret_cast<double2*>(base + lay.pairs_off);
   double* plast = reinterpret_cast<double*>(base + lay.plast_off);
-  double* rowpart = reinterpret_cast<double*>(base + lay.rowpart_off);
   double* grampart = reinterpret_cast<double*>(base + lay.grampart_off);
   const int64_t max_iters = opts->max_iters > 0 ? opts->max_iters : 10 * n;
   const int64_t max_outer = opts->max_outer > 0 ? opts->max_outer : max_iters;
@@ -445,7 +449,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
-  launch_setup(h->stream, h->d_ctl, Av, b, x, pairs, rowpart);
+  launch_setup(h->stream, h->d_ctl, Av, b, x, pairs, h->d_part);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
 
@@ -480,8 +484,8 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
       if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
       launch_gram_reduce(h->stream, h->d_ctl, sigma, nbg, grampart);
       launch_controller(h->stream, h->d_ctl, h->d_trace, sigma);
-      launch_recover(h->stream, h->d_ctl, n, pairs, plast, lay.ld, x);
-      launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, rowpart, 0);
+      launch_recover(h->stream, h->d_ctl, Av, pairs, plast, lay.ld, x);
+      launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, h->d_part, 0);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, 2 * sizeof(int32_t) + sizeof(int32_t),
@@ -506,7 +510,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   }
   HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
   if (status != ASSG_CONVERGED) {
-    launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, rowpart, 1);
+    launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, h->d_part, 1);
     HIP_OR_FAIL(h, hipGetLastError());
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
@@ -563,8 +567,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   if (st != ASSG_OK) return st;
   double* r = reinterpret_cast<double*>(base);
   double* p = r + lay.ld;
-  double* w = p + lay.ld;
-  double* rowpart = reinterpret_cast<double*>(base + lay.rowpart_off);
+  double* w = r + 2 * lay.ld;
   const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 1);
@@ -575,17 +578,17 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
-  launch_h_init(h->stream, h->d_ctl, Av, b, x, r, p, rowpart);
+  launch_h_init(h->stream, h->d_ctl, Av, b, x, r, p, h->d_part);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
   int batch = 4;
   int32_t status = ST_RUNNING;
   while (true) {
     for (int bi = 0; bi < batch; ++bi) {
-      launch_h_spmv(h->stream, h->d_ctl, Av, p, w, rowpart);
-      launch_h_update(h->stream, h->d_ctl, n, x, r, p, w, rowpart);
-      launch_h_dir(h->stream, h->d_ctl, n, r, p);
-      launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, rowpart, 0);
+      launch_h_spmv(h->stream, h->d_ctl, Av, p, w, h->d_part);
+      launch_h_update(h->stream, h->d_ctl, Av, x, r, p, w, h->d_part);
+      launch_h_dir(h->stream, h->d_ctl, Av, r, p);
+      launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, h->d_part, 0);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -597,7 +600,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   }
   HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
   if (status != ASSG_CONVERGED) {
-    launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, rowpart, 1);
+    launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, h->d_part, 1);
     HIP_OR_FAIL(h, hipGetLastError());
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));

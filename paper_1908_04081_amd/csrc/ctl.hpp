@@ -61,10 +61,6 @@ struct alignas(256) Ctl {
   // ------------------------------------------------------------- the Gram
   double G[MAXC * MAXC];                          // row-major, interleaved order
 
-  // ------------------------------------------------------------ reductions
-  double red;            // result of the last grid reduction
-  uint32_t counter;      // arrival counter of the last-block reductions
-  uint32_t pad_[3];
 };
 
 // Basis parameters of (2.3) for s levels (Section 2 monomial, (2.7) Newton,

@@ -65,12 +65,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 __device__ __forceinline__ int xcd_logical(int b, int nb) {
   return (b % NXCD) * (nb / NXCD) + b / NXCD;
 }
-// Contiguous tile range [t0, t1) of logical workgroup L out of nb over ntiles.
-__device__ __forceinline__ void tile_range(int L, int nb, int64_t ntiles, int64_t& t0,
-                                           int64_t& t1) {
-  t0 = (ntiles * L) / nb;
-  t1 = (ntiles * (L + 1)) / nb;
-}
 
 // ------------------------------------------------------ CSR-stream rows
 // Source vectors of a product: x[c] (one chain), the pair (x_P[c], x_R[c])
@@ -171,38 +165,28 @@ __device__ __forceinline__ void block_range(int32_t nblk, int32_t& b0, int32_t& 
   b1 = (int32_t)(((int64_t)nblk * (L + 1)) / gridDim.x);
 }
 
-// ------------------------------------------------ last-block reductions
-// Each workgroup stores its partial, then the last one to arrive sums all
-// partials in index order (deterministic for a fixed launch shape) and
-// returns true in thread 0 with the total in ``total``.
-__device__ __forceinline__ bool last_block_total(double part, double* partials, Ctl* ctl,
-                                                 double* total, double* sh) {
-  __shared__ bool am_last;
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = part;
-    __threadfence();
-    const uint32_t prev =
-        __hip_atomic_fetch_add(&ctl->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  // fixed-order sum: thread t sums partials t, t+NT, ...; then a fixed tree
+// ------------------------------------------------------ grid reductions
+// Grid kernels store one partial per workgroup (plain stores; the next
+// kernel sees them at the kernel boundary, so no cross-workgroup fences are
+// needed -- a device-scope release would write back the XCD's L2).  A
+// one-workgroup kernel then sums them in index order: thread t adds
+// partials t, t+NT, ... and the threads are combined by a fixed tree.
+template <int NT>
+__device__ __forceinline__ double finish_sum(const double* __restrict__ part, int n, double* sh) {
+  constexpr int U = 16;   // independent loads in flight per thread; adds stay in index order
   double s = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-    s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  s = wave_sum(s);
-  const int w = threadIdx.x / WAVE;
-  if ((threadIdx.x & (WAVE - 1)) == 0) sh[w] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) t += sh[i];
-    *total = t;
-    ctl->counter = 0u;   // ready for the next reduction on this stream
+  for (int base = threadIdx.x; base < n; base += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int i = base + k * NT;
+      v[k] = (i < n) ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) s += v[k];
   }
-  return threadIdx.x == 0;
+  return block_sum<NT>(s, sh);
 }
+
 
 }  // namespace assg

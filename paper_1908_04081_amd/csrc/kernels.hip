@@ -21,13 +21,6 @@
 
 namespace assg {
 
-int row_blocks(int64_t n) {
-  const int64_t ntiles = (n + TILE_ROWS - 1) / TILE_ROWS;
-  int64_t nb = ((ntiles + NXCD - 1) / NXCD) * NXCD;
-  if (nb > MAX_ROW_BLOCKS) nb = MAX_ROW_BLOCKS;
-  if (nb < NXCD) nb = NXCD;
-  return (int)nb;
-}
 
 void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk) {
   blk.clear();
@@ -40,6 +33,11 @@ void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk) {
       while (r < n && r - r0 < SB_ROWS && (int64_t)rp[r + 1] - rp[r0] <= SB_CAP) ++r;
     blk.push_back((int32_t)r);
   }
+}
+
+size_t reduce_doubles(int32_t nblk) {
+  const size_t g = ((size_t)nblk + NXCD - 1) / NXCD * NXCD;
+  return 2 * g + 64;
 }
 
 // Grid of a row-block kernel: one workgroup per block (rounded up to a
@@ -72,14 +70,6 @@ struct BlockRows {
   }
 };
 
-// Rows owned by this workgroup: tiles [t0, t1) of TILE_ROWS rows.
-struct RowIter {
-  int64_t t0, t1;
-  __device__ RowIter(int64_t n) {
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
-    tile_range(L, gridDim.x, (n + TILE_ROWS - 1) / TILE_ROWS, t0, t1);
-  }
-};
 
 // ------------------------------------------------------------------ SpMV
 __global__ __launch_bounds__(256) void k_spmv(CsrView A, const double* __restrict__ x,
@@ -106,13 +96,12 @@ void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y) {
 __global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CsrView A, const double* __restrict__ b,
                                                const double* __restrict__ x,
                                                double2* __restrict__ pairs,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ part) {
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
-  double part = 0.0;
-  int32_t b0, b1;
-  block_range(A.nblk, b0, b1);
-  for (int32_t bb = b0; bb < b1; ++bb) {
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  double my = 0.0;
+  if (bb < A.nblk) {
     const BlockRows br(A, bb);
     double bi = 0.0;
     if (br.own) bi = b[br.row];
@@ -122,19 +111,25 @@ __global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CsrView A, const double
     if (br.own) {
       const double ri = bi - ax;
       pairs[br.row] = make_double2(ri, ri);
-      part = fma(bi, bi, part);
+      my = bi * bi;
     }
-    __syncthreads();
   }
-  part = block_sum<256>(part, red);
-  double tot;
-  if (last_block_total(part, partials, ctl, &tot, red)) ctl->nb = sqrt(tot);
+  my = block_sum<256>(my, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = my;
+}
+
+__global__ __launch_bounds__(1024) void k_fin_setup(Ctl* ctl, const double* __restrict__ part,
+                                                    int n) {
+  __shared__ double sh[16];
+  const double t = finish_sum<1024>(part, n, sh);
+  if (threadIdx.x == 0) ctl->nb = sqrt(t);
 }
 
 void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
-                  double2* pairs, double* partials) {
-  hipLaunchKernelGGL(k_setup, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, b,
-                     x, pairs, partials);
+                  double2* pairs, double* part) {
+  const int g = block_grid(A, 1 << 30);
+  hipLaunchKernelGGL(k_setup, dim3(g), dim3(256), 0, s, ctl, A, b, x, pairs, part);
+  hipLaunchKernelGGL(k_fin_setup, dim3(1), dim3(1024), 0, s, ctl, part, g);
 }
 
 // ------------------------------------------------ matrix powers: one level
@@ -381,42 +376,44 @@ void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const do
 // (2.6): x += Y x', p = Y p', r = Y r' over the 2 s_k + 1 columns that carry
 // coordinates after s_k inner steps ((2.1): P_0..P_{s_k}, R_0..R_{s_k-1});
 // (p, r) overwrite basis level 0 row by row (each row is read before it is
-// written by the same thread).
-__global__ __launch_bounds__(ROW_THREADS) void k_recover(const Ctl* __restrict__ ctl, int64_t n,
-                                                         double2* __restrict__ pairs,
-                                                         const double* __restrict__ plast,
-                                                         int64_t ld, double* __restrict__ x) {
+// written by the same thread).  One workgroup per row block, one row per
+// thread, all basis loads of a row issued together.
+__global__ __launch_bounds__(256) void k_recover(const Ctl* __restrict__ ctl, CsrView A,
+                                                 double2* __restrict__ pairs,
+                                                 const double* __restrict__ plast, int64_t ld,
+                                                 double* __restrict__ x) {
   if (ctl->status != ST_RUNNING || ctl->skip_recover) return;
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  if (bb >= A.nblk) return;
+  const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
+  if ((int)threadIdx.x >= nr) return;
+  const int64_t row = (int64_t)r0 + threadIdx.x;
   const int sk = ctl->sk, sbar = ctl->sbar;
   const double* __restrict__ plevel =
       (sk == sbar) ? plast : reinterpret_cast<const double*>(pairs + (size_t)sk * ld);
   const int pstride = (sk == sbar) ? 1 : 2;
-  RowIter it(n);
-  for (int64_t t = it.t0; t < it.t1; ++t) {
-    const int64_t row = t * TILE_ROWS + threadIdx.x;
-    if (row >= n) continue;
-    double xs = 0.0, ps = 0.0, rs = 0.0;
-    for (int l = 0; l < sk; ++l) {
-      const double2 y = pairs[(size_t)l * ld + row];
-      xs = fma(ctl->cx[2 * l], y.x, xs);
-      xs = fma(ctl->cx[2 * l + 1], y.y, xs);
-      ps = fma(ctl->cp[2 * l], y.x, ps);
-      ps = fma(ctl->cp[2 * l + 1], y.y, ps);
-      rs = fma(ctl->cr[2 * l], y.x, rs);
-      rs = fma(ctl->cr[2 * l + 1], y.y, rs);
-    }
-    const double yl = plevel[pstride * row];
-    xs = fma(ctl->cx[2 * sk], yl, xs);
-    ps = fma(ctl->cp[2 * sk], yl, ps);
-    rs = fma(ctl->cr[2 * sk], yl, rs);
-    x[row] += xs;
-    pairs[row] = make_double2(ps, rs);
+  const double yl = plevel[pstride * row];
+  const double x0 = x[row];
+  double xs = 0.0, ps = 0.0, rs = 0.0;
+  for (int l = 0; l < sk; ++l) {
+    const double2 y = pairs[(size_t)l * ld + row];
+    xs = fma(ctl->cx[2 * l], y.x, xs);
+    xs = fma(ctl->cx[2 * l + 1], y.y, xs);
+    ps = fma(ctl->cp[2 * l], y.x, ps);
+    ps = fma(ctl->cp[2 * l + 1], y.y, ps);
+    rs = fma(ctl->cr[2 * l], y.x, rs);
+    rs = fma(ctl->cr[2 * l + 1], y.y, rs);
   }
+  xs = fma(ctl->cx[2 * sk], yl, xs);
+  ps = fma(ctl->cp[2 * sk], yl, ps);
+  rs = fma(ctl->cr[2 * sk], yl, rs);
+  x[row] = x0 + xs;
+  pairs[row] = make_double2(ps, rs);
 }
 
-void launch_recover(hipStream_t s, const Ctl* ctl, int64_t n, double2* pairs,
+void launch_recover(hipStream_t s, const Ctl* ctl, const CsrView& A, double2* pairs,
                     const double* plast, int64_t ld, double* x) {
-  hipLaunchKernelGGL(k_recover, dim3(row_blocks(n)), dim3(ROW_THREADS), 0, s, ctl, n, pairs,
+  hipLaunchKernelGGL(k_recover, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, ctl, A, pairs,
                      plast, ld, x);
 }
 
@@ -451,20 +448,16 @@ __device__ void commit_loop(Ctl* ctl, assg_trace_t* trace, bool checked, double 
   ctl->status = st;
 }
 
-__global__ __launch_bounds__(256) void k_check(Ctl* ctl, assg_trace_t* trace, CsrView A,
+__global__ __launch_bounds__(256) void k_check(const Ctl* ctl, CsrView A,
                                                const double* __restrict__ b,
                                                const double* __restrict__ x,
-                                               double* __restrict__ partials, int measure_only) {
+                                               double* __restrict__ part, int measure_only) {
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
-  if (!measure_only) {
-    if (ctl->status != ST_RUNNING) return;
-    if (!ctl->candidate) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) commit_loop(ctl, trace, false, -1.0);
-      return;
-    }
-  }
-  double part = 0.0;
+  if (!measure_only && (ctl->status != ST_RUNNING || !ctl->candidate)) return;
+  // a small grid looping over the row blocks: this kernel usually exits at
+  // once, and an empty launch of one workgroup per block costs ~15 us
+  double my = 0.0;
   int32_t b0, b1;
   block_range(A.nblk, b0, b1);
   for (int32_t bb = b0; bb < b1; ++bb) {
@@ -476,38 +469,55 @@ __global__ __launch_bounds__(256) void k_check(Ctl* ctl, assg_trace_t* trace, Cs
                                 red, ax, unused);
     if (br.own) {
       const double ri = bi - ax;
-      part = fma(ri, ri, part);
+      my = fma(ri, ri, my);
     }
     __syncthreads();
   }
-  part = block_sum<256>(part, red);
-  double tot;
-  if (last_block_total(part, partials, ctl, &tot, red)) {
-    const double rel = sqrt(tot) / ctl->nb;
+  my = block_sum<256>(my, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = my;
+}
+
+// End of an outer loop (or HSCG iteration): the true relative residual when
+// a candidate was flagged, then the commit.
+__global__ __launch_bounds__(1024) void k_fin_check(Ctl* ctl, assg_trace_t* trace,
+                                                    const double* __restrict__ part, int n,
+                                                    int measure_only) {
+  __shared__ double sh[16];
+  if (!measure_only && ctl->status != ST_RUNNING) return;
+  const bool checked = measure_only || ctl->candidate;
+  double t = 0.0;
+  if (checked) t = finish_sum<1024>(part, n, sh);
+  if (threadIdx.x == 0) {
+    const double rel = checked ? sqrt(t) / ctl->nb : -1.0;
     if (measure_only)
       ctl->relres_true = rel;
     else
-      commit_loop(ctl, trace, true, rel);
+      commit_loop(ctl, trace, checked, rel);
   }
 }
 
 void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A,
-                  const double* b, const double* x, double* partials, int measure_only) {
-  hipLaunchKernelGGL(k_check, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, trace,
-                     A, b, x, partials, measure_only);
+                  const double* b, const double* x, double* part, int measure_only) {
+  const int g = block_grid(A, 2048);
+  hipLaunchKernelGGL(k_check, dim3(g), dim3(256), 0, s, ctl, A, b, x, part, measure_only);
+  hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(1024), 0, s, ctl, trace, part, g, measure_only);
 }
 
 // ------------------------------------------------------------------ HSCG
+// Algorithm 1 with two kernels per iteration over the row blocks:
+//  k_h_spmv   p = r + beta p (evaluated at the gathered columns too, so no
+//             separate direction pass; p is double-buffered), w = A p and
+//             the p^T w sum -> alpha;
+//  k_h_update x += alpha p, r -= alpha w and the r^T r sum -> beta.
 __global__ __launch_bounds__(256) void k_h_init(Ctl* ctl, CsrView A, const double* __restrict__ b,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ r, double* __restrict__ p,
-                                                double* __restrict__ partials) {
+                                                double* __restrict__ part) {
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
-  double pb = 0.0, pr = 0.0;
-  int32_t b0, b1;
-  block_range(A.nblk, b0, b1);
-  for (int32_t bb = b0; bb < b1; ++bb) {
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  double mb = 0.0, mr = 0.0;
+  if (bb < A.nblk) {
     const BlockRows br(A, bb);
     double bi = 0.0;
     if (br.own) bi = b[br.row];
@@ -518,42 +528,47 @@ __global__ __launch_bounds__(256) void k_h_init(Ctl* ctl, CsrView A, const doubl
       const double ri = bi - ax;
       r[br.row] = ri;
       p[br.row] = ri;
-      pb = fma(bi, bi, pb);
-      pr = fma(ri, ri, pr);
+      mb = bi * bi;
+      mr = ri * ri;
     }
-    __syncthreads();
   }
-  // two sums: partials[0..nb) and partials[nb..2nb)
-  pb = block_sum<256>(pb, red);
-  pr = block_sum<256>(pr, red);
-  double tot;
-  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = pr;
-  if (last_block_total(pb, partials, ctl, &tot, red)) {
-    double rr = 0.0;
-    for (int i = 0; i < (int)gridDim.x; ++i)
-      rr += __hip_atomic_load(partials + gridDim.x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ctl->nb = sqrt(tot);
-    ctl->h_rho = rr;
+  mb = block_sum<256>(mb, red);
+  mr = block_sum<256>(mr, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = mb;
+    part[gridDim.x + blockIdx.x] = mr;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_fin_h_init(Ctl* ctl, const double* __restrict__ part,
+                                                     int n) {
+  __shared__ double sh[16];
+  const double tb = finish_sum<1024>(part, n, sh);
+  const double tr = finish_sum<1024>(part + n, n, sh);
+  if (threadIdx.x == 0) {
+    ctl->nb = sqrt(tb);
+    ctl->h_rho = tr;
+    ctl->h_beta = 0.0;
   }
 }
 
 void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
-                   double* r, double* p, double* partials) {
-  hipLaunchKernelGGL(k_h_init, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, b,
-                     x, r, p, partials);
+                   double* r, double* p, double* part) {
+  const int g = block_grid(A, 1 << 30);
+  hipLaunchKernelGGL(k_h_init, dim3(g), dim3(256), 0, s, ctl, A, b, x, r, p, part);
+  hipLaunchKernelGGL(k_fin_h_init, dim3(1), dim3(1024), 0, s, ctl, part, g);
 }
 
-// w = A p with the p^T w partial sum; the last workgroup forms alpha.
-__global__ __launch_bounds__(256) void k_h_spmv(Ctl* ctl, CsrView A, const double* __restrict__ p,
+__global__ __launch_bounds__(256) void k_h_spmv(const Ctl* ctl, CsrView A,
+                                                const double* __restrict__ p,
                                                 double* __restrict__ w,
-                                                double* __restrict__ partials) {
+                                                double* __restrict__ part) {
   if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
-  double part = 0.0;
-  int32_t b0, b1;
-  block_range(A.nblk, b0, b1);
-  for (int32_t bb = b0; bb < b1; ++bb) {
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  double my = 0.0;
+  if (bb < A.nblk) {
     const BlockRows br(A, bb);
     double pi = 0.0;
     if (br.own) pi = p[br.row];
@@ -562,52 +577,81 @@ __global__ __launch_bounds__(256) void k_h_spmv(Ctl* ctl, CsrView A, const doubl
                                 red, v, unused);
     if (br.own) {
       w[br.row] = v;
-      part = fma(pi, v, part);
+      my = pi * v;
     }
-    __syncthreads();
   }
-  part = block_sum<256>(part, red);
-  double pw;
-  if (last_block_total(part, partials, ctl, &pw, red)) {
-    if (!(pw > 0.0) || !isfinite(pw)) {
+  my = block_sum<256>(my, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = my;
+}
+
+__global__ __launch_bounds__(1024) void k_fin_alpha(Ctl* ctl, const double* __restrict__ part,
+                                                    int n) {
+  if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
+  __shared__ double sh[16];
+  const double pw = finish_sum<1024>(part, n, sh);
+  if (threadIdx.x == 0) {
+    if (!(pw > 0.0) || !isfinite(pw))
       ctl->pending = isfinite(pw) ? ASSG_BREAKDOWN : ASSG_DIVERGED;
-    } else {
+    else
       ctl->h_alpha = ctl->h_rho / pw;
-    }
   }
 }
 
 void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, const double* p, double* w,
-                   double* partials) {
-  hipLaunchKernelGGL(k_h_spmv, dim3(block_grid(A, MAX_ROW_BLOCKS)), dim3(256), 0, s, ctl, A, p,
-                     w, partials);
+                   double* part) {
+  const int g = block_grid(A, 1 << 30);
+  hipLaunchKernelGGL(k_h_spmv, dim3(g), dim3(256), 0, s, ctl, A, p, w, part);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctl, part, g);
 }
 
-// x += alpha p; r -= alpha w; r^T r partial; the last workgroup forms beta
-// and the updated relative residual.
-__global__ __launch_bounds__(ROW_THREADS) void k_h_update(Ctl* ctl, int64_t n,
-                                                          double* __restrict__ x,
-                                                          double* __restrict__ r,
-                                                          const double* __restrict__ p,
-                                                          const double* __restrict__ w,
-                                                          double* __restrict__ partials) {
+// p = r + beta p, one row per thread.
+__global__ __launch_bounds__(256) void k_h_dir(const Ctl* ctl, CsrView A,
+                                               const double* __restrict__ r,
+                                               double* __restrict__ p) {
   if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
-  __shared__ double sh[ROW_THREADS / WAVE];
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  if (bb >= A.nblk) return;
+  const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
+  if ((int)threadIdx.x >= nr) return;
+  const int64_t row = (int64_t)r0 + threadIdx.x;
+  p[row] = r[row] + ctl->h_beta * p[row];
+}
+
+void launch_h_dir(hipStream_t s, const Ctl* ctl, const CsrView& A, const double* r, double* p) {
+  hipLaunchKernelGGL(k_h_dir, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, ctl, A, r, p);
+}
+
+__global__ __launch_bounds__(256) void k_h_update(const Ctl* ctl, CsrView A,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ part) {
+  if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
+  __shared__ double red[4];
   const double alpha = ctl->h_alpha;
-  double part = 0.0;
-  RowIter it(n);
-  for (int64_t t = it.t0; t < it.t1; ++t) {
-    const int64_t row = t * TILE_ROWS + threadIdx.x;
-    if (row >= n) continue;
-    const double q = alpha * p[row];
-    x[row] += q;
-    const double ri = r[row] - alpha * w[row];
-    r[row] = ri;
-    part = fma(ri, ri, part);
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  double my = 0.0;
+  if (bb < A.nblk) {
+    const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
+    if ((int)threadIdx.x < nr) {
+      const int64_t row = (int64_t)r0 + threadIdx.x;
+      const double pi = p[row], wi = w[row], xi = x[row], ri = r[row];
+      x[row] = xi + alpha * pi;
+      const double rn = ri - alpha * wi;
+      r[row] = rn;
+      my = rn * rn;
+    }
   }
-  part = block_sum<ROW_THREADS>(part, sh);
-  double rr;
-  if (last_block_total(part, partials, ctl, &rr, sh)) {
+  my = block_sum<256>(my, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = my;
+}
+
+__global__ __launch_bounds__(1024) void k_fin_beta(Ctl* ctl, const double* __restrict__ part,
+                                                   int n) {
+  if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
+  __shared__ double sh[16];
+  const double rr = finish_sum<1024>(part, n, sh);
+  if (threadIdx.x == 0) {
     const double beta = rr / ctl->h_rho;
     ctl->h_rho = rr;
     ctl->h_beta = beta;
@@ -623,26 +667,11 @@ __global__ __launch_bounds__(ROW_THREADS) void k_h_update(Ctl* ctl, int64_t n,
   }
 }
 
-void launch_h_update(hipStream_t s, Ctl* ctl, int64_t n, double* x, double* r, const double* p,
-                     const double* w, double* partials) {
-  hipLaunchKernelGGL(k_h_update, dim3(row_blocks(n)), dim3(ROW_THREADS), 0, s, ctl, n, x, r, p,
-                     w, partials);
-}
-
-__global__ __launch_bounds__(ROW_THREADS) void k_h_dir(const Ctl* ctl, int64_t n,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ p) {
-  if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
-  const double beta = ctl->h_beta;
-  RowIter it(n);
-  for (int64_t t = it.t0; t < it.t1; ++t) {
-    const int64_t row = t * TILE_ROWS + threadIdx.x;
-    if (row < n) p[row] = r[row] + beta * p[row];
-  }
-}
-
-void launch_h_dir(hipStream_t s, const Ctl* ctl, int64_t n, const double* r, double* p) {
-  hipLaunchKernelGGL(k_h_dir, dim3(row_blocks(n)), dim3(ROW_THREADS), 0, s, ctl, n, r, p);
+void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, double* r,
+                     const double* p, const double* w, double* part) {
+  const int g = block_grid(A, 1 << 30);
+  hipLaunchKernelGGL(k_h_update, dim3(g), dim3(256), 0, s, ctl, A, x, r, p, w, part);
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctl, part, g);
 }
 
 // ----------------------------------------------------- basis/Gram helpers

@@ -11,10 +11,6 @@
 
 namespace assg {
 
-constexpr int TILE_ROWS = 256;     // rows per tile of the row kernels
-constexpr int ROW_THREADS = 256;   // threads per workgroup of the row kernels
-constexpr int MAX_ROW_BLOCKS = 2048;
-
 // Row blocks of the CSR-stream kernels: at most SB_ROWS rows and SB_CAP
 // nonzeros each, except single rows longer than SB_CAP.
 constexpr int SB_ROWS = 256;
@@ -34,16 +30,16 @@ struct CsrView {
 // fewer than SB_ROWS rows and at most SB_CAP nonzeros.
 void make_blocks(const int32_t* row_ptr, int64_t n, std::vector<int32_t>& blk);
 
-// Launch shape of the streaming row kernels for n rows: a multiple of 8
-// workgroups (XCD-aware mapping), at most MAX_ROW_BLOCKS, each owning a
-// contiguous range of 256-row tiles.
-int row_blocks(int64_t n);
 
 void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
 
+// Per-workgroup partial sums of the grid reductions over the row-block grid
+// (two sums for the HSCG start).
+size_t reduce_doubles(int32_t nblk);
+
 // r = b - A x, pairs[0] = (r, r), ctl->nb = ||b||.
 void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
-                  double2* pairs, double* partials);
+                  double2* pairs, double* part);
 
 // Two-chain sweep producing basis level ``level`` (1 <= level < sbar).
 void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, double2* pairs,
@@ -57,23 +53,25 @@ void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const do
 
 void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma);
 
-void launch_recover(hipStream_t s, const Ctl* ctl, int64_t n, double2* pairs,
+void launch_recover(hipStream_t s, const Ctl* ctl, const CsrView& A, double2* pairs,
                     const double* plast, int64_t ld, double* x);
 
 // True relative residual when the loop's updated residual reached tol, then
 // commit of the loop's outcome.  With ``measure_only`` it only stores
 // ||b - A x|| / ||b|| in ctl->relres_true.
 void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A,
-                  const double* b, const double* x, double* partials, int measure_only);
+                  const double* b, const double* x, double* part, int measure_only);
 
-// HSCG (Algorithm 1).
+// HSCG (Algorithm 1): k_h_spmv forms w = A p and p^T w (-> alpha),
+// k_h_update x += alpha p, r -= alpha w and r^T r (-> beta), k_h_dir
+// p = r + beta p.
 void launch_h_init(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
-                   double* r, double* p, double* partials);
+                   double* r, double* p, double* part);
 void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, const double* p, double* w,
-                   double* partials);
-void launch_h_update(hipStream_t s, Ctl* ctl, int64_t n, double* x, double* r, const double* p,
-                     const double* w, double* partials);
-void launch_h_dir(hipStream_t s, const Ctl* ctl, int64_t n, const double* r, double* p);
+                   double* part);
+void launch_h_dir(hipStream_t s, const Ctl* ctl, const CsrView& A, const double* r, double* p);
+void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, double* r,
+                     const double* p, const double* w, double* part);
 
 // Helpers of assg_basis_gram.
 void launch_pair_init(hipStream_t s, int64_t n, const double* p, const double* r, double2* pairs);
