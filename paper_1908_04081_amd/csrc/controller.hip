@@ -16,123 +16,124 @@
 
 namespace assg {
 
-__host__ __device__ constexpr int scratch_offset(int l) {
+__host__ __device__ constexpr int scratch_offset(int l) {   // rows of the blocks before block l
   int o = 0;
-  for (int j = 1; j < l; ++j) o += (2 * j + 1) * (2 * j + 1);
+  for (int j = 1; j < l; ++j) o += 2 * j + 1;
   return o;
 }
-constexpr int SCRATCH = scratch_offset(MAXS + 1);
+constexpr int SCRATCH_ROWS = scratch_offset(MAXS + 1);   // 288 rows of MAXC doubles
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e) below x.
-__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x,
-                                           double pivmin) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int cnt = q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-  }
-  return cnt;
-}
-
-// sqrt(lambda_max / lambda_min) of the symmetric n x n matrix T (row-major,
-// LDS, destroyed); +inf when lambda_min <= 0.  One wave; scratch vectors
-// v, w, d, e2 hold MAXC doubles each.
-__device__ double kappa_wave(double* T, int n, int lane, double* v, double* w, double* d,
-                             double* e2) {
-  // Householder reduction to tridiagonal form
+// sqrt(lambda_max / lambda_min) of the symmetric n x n matrix T (LDS, row
+// stride MAXC, columns n..MAXC-1 zero, destroyed); +inf when lambda_min <= 0.
+// One wave: Householder reduction to tridiagonal form (lane i owns row i;
+// vectors are held one entry per lane and broadcast with readlane), then
+// Sturm-count multisection for the two extreme eigenvalues (lanes 0..31
+// bracket lambda_min, lanes 32..63 lambda_max, 33 sub-intervals per round)
+// down to a width of 2u times the Gershgorin scale, the accuracy any
+// backward-stable eigensolver attains.
+__device__ double kappa_wave(double* T, int n, int lane, double* dsh, double* esh) {
+  const int rowoff = (lane < n ? lane : 0) * MAXC;
   for (int k = 0; k + 2 < n; ++k) {
     const int m0 = k + 1;
     const bool in = (lane >= m0) && (lane < n);
-    const double xi = in ? T[lane * n + k] : 0.0;
-    const double x0 = T[m0 * n + k];
-    const double ss = wave_sum((lane > m0 && lane < n) ? xi * xi : 0.0);
-    if (lane == 0) d[k] = T[k * n + k];
+    const double xi = in ? T[rowoff + k] : 0.0;
+    const double x0 = readlane_d(xi, m0);
+    const double ss = wave_sum_dpp((lane > m0 && lane < n) ? xi * xi : 0.0);
+    if (lane == 0) dsh[k] = T[k * MAXC + k];
     if (ss == 0.0) {
-      if (lane == 0) e2[k] = x0 * x0;
-      wave_lds_sync();
+      if (lane == 0) esh[k] = x0 * x0;
       continue;
     }
     const double nrm = sqrt(x0 * x0 + ss);
     const double alpha = (x0 > 0.0) ? -nrm : nrm;
     const double vi = in ? (lane == m0 ? x0 - alpha : xi) : 0.0;
-    const double vtv = (x0 - alpha) * (x0 - alpha) + ss;
-    const double beta = 2.0 / vtv;
-    if (lane < MAXC) v[lane] = vi;
-    wave_lds_sync();
-    double pi = 0.0;
-    if (in)
-      for (int j = m0; j < n; ++j) pi = fma(T[lane * n + j], v[j], pi);
-    pi *= beta;
-    const double K = 0.5 * beta * wave_sum(pi * vi);
+    const double beta = 2.0 / ((x0 - alpha) * (x0 - alpha) + ss);
+    double pa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < MAXC; ++j) pa[j & 3] = fma(T[rowoff + j], readlane_d(vi, j), pa[j & 3]);
+    double pi = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+    pi = in ? pi * beta : 0.0;
+    const double K = 0.5 * beta * wave_sum_dpp(pi * vi);
     const double wi = pi - K * vi;
-    if (lane < MAXC) w[lane] = wi;
-    wave_lds_sync();
-    if (in)
-      for (int j = m0; j < n; ++j) T[lane * n + j] -= vi * w[j] + wi * v[j];
-    if (lane == 0) e2[k] = alpha * alpha;
+    if (in) {
+#pragma unroll
+      for (int j = 0; j < MAXC; ++j)
+        T[rowoff + j] -= vi * readlane_d(wi, j) + wi * readlane_d(vi, j);
+    }
+    if (lane == 0) esh[k] = alpha * alpha;
     wave_lds_sync();
   }
   if (lane == 0) {
-    d[n - 2] = T[(n - 2) * n + (n - 2)];
-    const double el = T[(n - 1) * n + (n - 2)];
-    e2[n - 2] = el * el;
-    d[n - 1] = T[(n - 1) * n + (n - 1)];
+    dsh[n - 2] = T[(n - 2) * MAXC + (n - 2)];
+    const double el = T[(n - 1) * MAXC + (n - 2)];
+    esh[n - 2] = el * el;
+    dsh[n - 1] = T[(n - 1) * MAXC + (n - 1)];
   }
   wave_lds_sync();
 
-  // Gershgorin interval and pivot guard
   double glo = INFINITY, ghi = -INFINITY, emax = 0.0;
   if (lane < n) {
-    const double el = (lane > 0) ? sqrt(e2[lane - 1]) : 0.0;
-    const double er = (lane < n - 1) ? sqrt(e2[lane]) : 0.0;
-    glo = d[lane] - el - er;
-    ghi = d[lane] + el + er;
-    emax = (lane < n - 1) ? e2[lane] : 0.0;
+    const double el = (lane > 0) ? sqrt(esh[lane - 1]) : 0.0;
+    const double er = (lane < n - 1) ? sqrt(esh[lane]) : 0.0;
+    glo = dsh[lane] - el - er;
+    ghi = dsh[lane] + el + er;
+    emax = (lane < n - 1) ? esh[lane] : 0.0;
   }
-  glo = wave_min(glo);
-  ghi = wave_max(ghi);
-  emax = wave_max(emax);
+  glo = wave_min_dpp(glo);
+  ghi = wave_max_dpp(ghi);
+  emax = wave_max_dpp(emax);
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
-  const double pad = 4.0 * UNIT_ROUNDOFF * fmax(fabs(glo), fabs(ghi)) + pivmin;
+  const double scale = fmax(fabs(glo), fabs(ghi));
+  const double pad = 4.0 * UNIT_ROUNDOFF * scale + pivmin;
   glo -= pad;
   ghi += pad;
+  const double width = 2.0 * UNIT_ROUNDOFF * scale + pivmin;
 
-  // multisection: lanes 0..31 bracket lambda_min, lanes 32..63 lambda_max
+  // the tridiagonal in registers, entry i in lane i, broadcast by readlane
+  const double dl = (lane < n) ? dsh[lane] : 0.0;
+  const double el2 = (lane < n - 1) ? esh[lane] : 0.0;
   double loA = glo, hiA = ghi, loB = glo, hiB = ghi;
   const int j = lane & 31;
   const bool first = lane < 32;
   for (int it = 0; it < 16; ++it) {
     const double L = first ? loA : loB;
     const double H = first ? hiA : hiB;
-    const double x = L + (H - L) * (double)(j + 1) / 33.0;
+    const double x = L + (H - L) * (double)(j + 1) * (1.0 / 33.0);
     const int target = first ? 1 : n;
-    const bool ok = sturm_count(d, e2, n, x, pivmin) >= target;
-    const uint64_t mask = __ballot(ok);
+    double q = readlane_d(dl, 0) - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+#pragma unroll
+    for (int i = 1; i < MAXC; ++i) {
+      if (i < n) {
+        double rq = __builtin_amdgcn_rcp(q);          // ~26-bit seed
+        rq = fma(rq, fma(-q, rq, 1.0), rq);             // one Newton step: ~full precision
+        q = (readlane_d(dl, i) - x) - readlane_d(el2, i - 1) * rq;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+    }
+    const uint64_t mask = __ballot(cnt >= target);
     const uint32_t ma = (uint32_t)(mask & 0xffffffffu), mb = (uint32_t)(mask >> 32);
     if (ma == 0u) {
-      loA = loA + (hiA - loA) * 32.0 / 33.0;
+      loA = loA + (hiA - loA) * (32.0 / 33.0);
     } else {
       const int j0 = __builtin_ctz(ma);
-      const double nh = loA + (hiA - loA) * (double)(j0 + 1) / 33.0;
-      const double nl = (j0 > 0) ? loA + (hiA - loA) * (double)j0 / 33.0 : loA;
+      const double nh = loA + (hiA - loA) * (double)(j0 + 1) * (1.0 / 33.0);
+      const double nl = (j0 > 0) ? loA + (hiA - loA) * (double)j0 * (1.0 / 33.0) : loA;
       loA = nl;
       hiA = nh;
     }
     if (mb == 0u) {
-      loB = loB + (hiB - loB) * 32.0 / 33.0;
+      loB = loB + (hiB - loB) * (32.0 / 33.0);
     } else {
       const int j0 = __builtin_ctz(mb);
-      const double nh = loB + (hiB - loB) * (double)(j0 + 1) / 33.0;
-      const double nl = (j0 > 0) ? loB + (hiB - loB) * (double)j0 / 33.0 : loB;
+      const double nh = loB + (hiB - loB) * (double)(j0 + 1) * (1.0 / 33.0);
+      const double nl = (j0 > 0) ? loB + (hiB - loB) * (double)j0 * (1.0 / 33.0) : loB;
       loB = nl;
       hiB = nh;
     }
-    if (hiA - loA <= 2.0 * UNIT_ROUNDOFF * fmax(fabs(loA), fabs(hiA)) &&
-        hiB - loB <= 2.0 * UNIT_ROUNDOFF * fmax(fabs(loB), fabs(hiB)))
-      break;
+    if (hiA - loA <= width && hiB - loB <= width) break;
   }
   const double lmin = 0.5 * (loA + hiA);
   const double lmax = 0.5 * (loB + hiB);
@@ -142,44 +143,48 @@ __device__ double kappa_wave(double* T, int n, int lane, double* v, double* w, d
 
 // (B v)_i for the change of basis (2.5) of s~ levels, interleaved order:
 // P_j = 2j, R_j = 2j+1; block column j holds theta_j (diagonal), gamma_j
-// (next level), mu_{j-1} (previous level); the last P and last R columns are 0.
-__device__ __forceinline__ double apply_B(const double* v, int st, int lane, const double* th,
+// (next level), mu_{j-1} (previous level); the last P and last R columns
+// are 0.  Lane i holds v_i; neighbours two lanes away come by shuffles.
+__device__ __forceinline__ double apply_B(double v, int st, int lane, const double* th,
                                           const double* ga, const double* mu) {
+  const double vm2 = __shfl_up(v, 2, 64);
+  const double vp2 = __shfl_down(v, 2, 64);
   const int n = 2 * st + 1;
   if (lane >= n) return 0.0;
   const int j = lane >> 1;
   const int lastcol = (lane & 1) ? st - 2 : st - 1;
   double r = 0.0;
-  if (j >= 1 && j - 1 <= lastcol) r = fma(ga[j - 1], v[lane - 2], r);
-  if (j <= lastcol) r = fma(th[j], v[lane], r);
-  if (j + 1 <= lastcol) r = fma(mu[j], v[lane + 2], r);
+  if (j >= 1 && j - 1 <= lastcol) r = fma(ga[j - 1], vm2, r);
+  if (j <= lastcol) r = fma(th[j], v, r);
+  if (j + 1 <= lastcol) r = fma(mu[j], vp2, r);
   return r;
 }
 
-// (G v)_lane over the leading n entries.
-__device__ __forceinline__ double gmv(const double* G, const double* v, int n, int lane) {
-  double s = 0.0;
-  if (lane < n)
-    for (int c = 0; c < n; ++c) s = fma(G[lane * MAXC + c], v[c], s);
+// (G v)_lane with lane i holding row i of G in registers and v_i.
+__device__ __forceinline__ double gmv(const double* grow, double v) {
+  double s = 0.0;   // column order, one chain (as a row of a plain matrix-vector product)
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) s = fma(grow[c], readlane_d(v, c), s);
   return s;
 }
 
-__global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
+constexpr int CTL_WAVES = 8;   // wave w estimates blocks w+1, w+9 (256 VGPRs per lane)
+
+__global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__ ctl,
                                                      assg_trace_t* __restrict__ trace) {
   if (ctl->status != ST_RUNNING) return;
   __shared__ double sG[MAXC * MAXC];
-  __shared__ double sScr[SCRATCH];
-  __shared__ double sVec[MAXS][4][MAXC];
+  __shared__ double sScr[SCRATCH_ROWS * MAXC];
+  __shared__ double sDE[MAXS][2][MAXC];
   __shared__ double sKappa[MAXS + 2];
   __shared__ double sTh[MAXS], sGa[MAXS], sMu[MAXS];
-  __shared__ double vp[MAXC], vr[MAXC], vx[MAXC], vt[MAXC];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int sbar = ctl->sbar;
   const int nc = 2 * sbar + 1;
-  for (int i = tid; i < nc * nc; i += blockDim.x) {
-    const int a = i / nc, b = i % nc;
-    sG[a * MAXC + b] = ctl->G[a * MAXC + b];
+  for (int i = tid; i < MAXC * MAXC; i += blockDim.x) {
+    const int a = i / MAXC, b = i % MAXC;
+    sG[i] = (a < nc && b < nc) ? ctl->G[a * MAXC + b] : 0.0;
   }
   if (tid < MAXS) {
     sTh[tid] = ctl->theta[tid];
@@ -189,14 +194,16 @@ __global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
   if (tid < MAXS + 2) sKappa[tid] = INFINITY;
   __syncthreads();
 
-  // ---- kappa(Y_{k,l}) for l = 1..sbar, one wave each
-  if (wave < sbar) {
-    const int l = wave + 1, n = 2 * l + 1;
-    double* T = sScr + scratch_offset(l);
-    for (int i = lane; i < n * n; i += 64) T[i] = sG[(i / n) * MAXC + (i % n)];
+  // ---- kappa(Y_{k,l}) for l = 1..sbar: wave w takes l = w+1 and l = w+9
+  for (int l = wave + 1; l <= sbar; l += CTL_WAVES) {
+    const int n = 2 * l + 1;
+    double* T = sScr + scratch_offset(l) * MAXC;
+    for (int i = lane; i < n * MAXC; i += 64) {
+      const int a = i / MAXC, b = i % MAXC;
+      T[i] = (b < n) ? sG[a * MAXC + b] : 0.0;
+    }
     wave_lds_sync();
-    const double kap = kappa_wave(T, n, lane, sVec[wave][0], sVec[wave][1], sVec[wave][2],
-                                  sVec[wave][3]);
+    const double kap = kappa_wave(T, n, lane, sDE[l - 1][0], sDE[l - 1][1]);
     if (lane == 0) sKappa[l] = kap;
   }
   __syncthreads();
@@ -218,13 +225,14 @@ __global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
   }
   const int n = 2 * st + 1;
 
-  // ---- inner loop (interleaved coordinates; lane i owns coordinate i)
-  if (lane < MAXC) {
-    vp[lane] = (lane == 0) ? 1.0 : 0.0;
-    vr[lane] = (lane == 1) ? 1.0 : 0.0;
-    vx[lane] = 0.0;
-  }
-  wave_lds_sync();
+  // ---- inner loop (interleaved coordinates; lane i owns coordinate i and
+  // row i of G, zero beyond the 2 s~ + 1 leading ones)
+  double grow[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) grow[c] = (lane < n && c < n) ? sG[lane * MAXC + c] : 0.0;
+  double vp = (lane == 0) ? 1.0 : 0.0;
+  double vr = (lane == 1) ? 1.0 : 0.0;
+  double vx = 0.0;
   double rGr = rGr0;
   double phi = sqrt(rGr) / nb;
   double psi = ctl->psi;
@@ -238,32 +246,17 @@ __global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
   for (int j = 0; j < st; ++j) {
     sk = j + 1;
     const double bp = apply_B(vp, st, lane, sTh, sGa, sMu);
-    if (lane < MAXC) vt[lane] = bp;
-    wave_lds_sync();
-    const double gb = gmv(sG, vt, n, lane);
-    const double den = wave_sum(lane < n ? vp[lane] * gb : 0.0);
+    const double den = wave_sum_dpp(vp * gmv(grow, bp));
     if (!isfinite(den)) { outcome = ASSG_DIVERGED; break; }
     if (den <= 0.0 || rGr <= 0.0) { outcome = ASSG_BREAKDOWN; break; }
     const double alpha = rGr / den;
-    const double q = (lane < n) ? alpha * vp[lane] : 0.0;
-    wave_lds_sync();
-    if (lane < MAXC) {
-      vx[lane] += q;
-      vt[lane] = q;
-    }
-    wave_lds_sync();
-    const double bq = apply_B(vt, st, lane, sTh, sGa, sMu);
-    const double rnew = (lane < n) ? vr[lane] - bq : 0.0;
-    wave_lds_sync();
-    if (lane < MAXC) vr[lane] = rnew;
-    wave_lds_sync();
-    const double gr = gmv(sG, vr, n, lane);
-    const double rGr_new = fmax(wave_sum(lane < n ? rnew * gr : 0.0), 0.0);
+    const double q = (lane < n) ? alpha * vp : 0.0;
+    vx += q;
+    const double rnew = (lane < n) ? vr - apply_B(q, st, lane, sTh, sGa, sMu) : 0.0;
+    vr = rnew;
+    const double rGr_new = fmax(wave_sum_dpp(rnew * gmv(grow, rnew)), 0.0);
     const double beta = rGr_new / rGr;
-    const double pnew = (lane < n) ? rnew + beta * vp[lane] : 0.0;
-    wave_lds_sync();
-    if (lane < MAXC) vp[lane] = pnew;
-    wave_lds_sync();
+    vp = (lane < n) ? rnew + beta * vp : 0.0;
     rGr = rGr_new;
     const double rho = sqrt(rGr) / nb;
     phi = fmax(phi, rho);
@@ -314,9 +307,9 @@ __global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
   // ---- results
   if (lane < MAXC) {
     const bool keep = lane < n;
-    ctl->cx[lane] = keep ? vx[lane] : 0.0;
-    ctl->cr[lane] = keep ? vr[lane] : 0.0;
-    ctl->cp[lane] = keep ? vp[lane] : 0.0;
+    ctl->cx[lane] = keep ? vx : 0.0;
+    ctl->cr[lane] = keep ? vr : 0.0;
+    ctl->cp[lane] = keep ? vp : 0.0;
   }
   if (lane < MAXS) ctl->kappa[lane] = (lane < sbar) ? sKappa[lane + 1] : 0.0;
   if (lane == 0) {
@@ -379,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_controller(Ctl* __restrict__ ctl,
 }
 
 void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma) {
-  const int waves = sigma < 1 ? 1 : sigma;
+  const int waves = sigma < 1 ? 1 : (sigma < CTL_WAVES ? sigma : CTL_WAVES);
   hipLaunchKernelGGL(k_controller, dim3(1), dim3(64 * waves), 0, s, ctl, trace);
 }
 

@@ -33,6 +33,43 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// ------------------------------------------- DPP/readlane wave reductions
+// Cross-lane moves within rows of 16 lanes by DPP (no LDS crossbar), the
+// four row results combined through readlane.  The order of the additions
+// is fixed, so the result is deterministic and uniform across the wave.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_min_dpp(double v) {
+  v = fmin(v, dpp_mov<0xB1>(v));
+  v = fmin(v, dpp_mov<0x4E>(v));
+  v = fmin(v, dpp_mov<0x141>(v));
+  v = fmin(v, dpp_mov<0x140>(v));
+  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_mov<0xB1>(v));
+  v = fmax(v, dpp_mov<0x4E>(v));
+  v = fmax(v, dpp_mov<0x141>(v));
+  v = fmax(v, dpp_mov<0x140>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 // Orders LDS traffic between lanes of one wave (a wave executes its LDS
 // operations in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_sync() {

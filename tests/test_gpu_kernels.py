@@ -162,8 +162,11 @@ def test_controller_replays_oracle_loops(env, basis):
         assert bool(res.candidate) == bool(rec["candidate"])
         kap_o = np.array(rec["kappa"])
         kap_g = np.array(res.kappa[:sbar])
+        # kappa(Y) = sqrt(kappa(G)); any backward-stable eigensolver gets
+        # lambda_min(G) to about u*||G||, i.e. kappa(Y) to about u*kappa(G)
         fin = np.isfinite(kap_o) & (kap_o < 1e6)
-        np.testing.assert_allclose(kap_g[fin], kap_o[fin], rtol=1e-6)
+        tol = 1e-12 + 16 * 2.0 ** -53 * kap_o[fin] ** 2
+        assert np.all(np.abs(kap_g[fin] - kap_o[fin]) <= tol * kap_o[fin]), (k, kap_g, kap_o)
         np.testing.assert_allclose(res.alpha[:res.sk], rec["alphas"], rtol=1e-12)
         np.testing.assert_allclose(res.beta[:res.sk], rec["betas"], rtol=1e-10)
         st = res.stilde
@@ -173,7 +176,7 @@ def test_controller_replays_oracle_loops(env, basis):
             assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), (k, name)
         if k + 1 < len(tr):
             nxt = tr[k + 1]["state_in"]
-            np.testing.assert_allclose(S.psi, nxt["psi"], rtol=1e-12)
+            np.testing.assert_allclose(S.psi, nxt["psi"], rtol=1e-10)
             np.testing.assert_allclose(S.c, nxt["c"], rtol=1e-10)
             if np.isfinite(nxt["lmax"]):
                 np.testing.assert_allclose([S.lmin, S.lmax], [nxt["lmin"], nxt["lmax"]],
