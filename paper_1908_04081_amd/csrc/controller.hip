@@ -31,7 +31,9 @@ constexpr int SCRATCH_ROWS = scratch_offset(MAXS + 1);   // 288 rows of MAXC dou
 // bracket lambda_min, lanes 32..63 lambda_max, 33 sub-intervals per round)
 // down to a width of 2u times the Gershgorin scale, the accuracy any
 // backward-stable eigensolver attains.
-__device__ double kappa_wave(double* T, int n, int lane, double* dsh, double* esh) {
+template <int N>
+__device__ double kappa_wave(double* T, int lane, double* dsh, double* esh) {
+  constexpr int n = N;
   const int rowoff = (lane < n ? lane : 0) * MAXC;
   for (int k = 0; k + 2 < n; ++k) {
     const int m0 = k + 1;
@@ -50,14 +52,14 @@ __device__ double kappa_wave(double* T, int n, int lane, double* dsh, double* es
     const double beta = 2.0 / ((x0 - alpha) * (x0 - alpha) + ss);
     double pa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < MAXC; ++j) pa[j & 3] = fma(T[rowoff + j], readlane_d(vi, j), pa[j & 3]);
+    for (int j = 0; j < N; ++j) pa[j & 3] = fma(T[rowoff + j], readlane_d(vi, j), pa[j & 3]);
     double pi = (pa[0] + pa[1]) + (pa[2] + pa[3]);
     pi = in ? pi * beta : 0.0;
     const double K = 0.5 * beta * wave_sum_dpp(pi * vi);
     const double wi = pi - K * vi;
     if (in) {
 #pragma unroll
-      for (int j = 0; j < MAXC; ++j)
+      for (int j = 0; j < N; ++j)
         T[rowoff + j] -= vi * readlane_d(wi, j) + wi * readlane_d(vi, j);
     }
     if (lane == 0) esh[k] = alpha * alpha;
@@ -104,14 +106,12 @@ __device__ double kappa_wave(double* T, int n, int lane, double* dsh, double* es
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
 #pragma unroll
-    for (int i = 1; i < MAXC; ++i) {
-      if (i < n) {
-        double rq = __builtin_amdgcn_rcp(q);          // ~26-bit seed
-        rq = fma(rq, fma(-q, rq, 1.0), rq);             // one Newton step: ~full precision
-        q = (readlane_d(dl, i) - x) - readlane_d(el2, i - 1) * rq;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-      }
+    for (int i = 1; i < N; ++i) {
+      double rq = __builtin_amdgcn_rcp(q);            // ~26-bit seed
+      rq = fma(rq, fma(-q, rq, 1.0), rq);               // one Newton step: ~full precision
+      q = (readlane_d(dl, i) - x) - readlane_d(el2, i - 1) * rq;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
     }
     const uint64_t mask = __ballot(cnt >= target);
     const uint32_t ma = (uint32_t)(mask & 0xffffffffu), mb = (uint32_t)(mask >> 32);
@@ -194,8 +194,11 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   if (tid < MAXS + 2) sKappa[tid] = INFINITY;
   __syncthreads();
 
-  // ---- kappa(Y_{k,l}) for l = 1..sbar: wave w takes l = w+1 and l = w+9
-  for (int l = wave + 1; l <= sbar; l += CTL_WAVES) {
+  // ---- kappa(Y_{k,l}) for l = 1..sbar, largest blocks first: wave w takes
+  // l = sbar - w, then l = sbar - 15 + w (snake order balances the waves)
+  for (int pass = 0; pass < 2; ++pass) {
+    const int l = (pass == 0) ? sbar - wave : sbar - (2 * CTL_WAVES - 1) + wave;
+    if (l < 1 || (pass == 1 && l > sbar - CTL_WAVES)) continue;
     const int n = 2 * l + 1;
     double* T = sScr + scratch_offset(l) * MAXC;
     for (int i = lane; i < n * MAXC; i += 64) {
@@ -203,7 +206,27 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       T[i] = (b < n) ? sG[a * MAXC + b] : 0.0;
     }
     wave_lds_sync();
-    const double kap = kappa_wave(T, n, lane, sDE[l - 1][0], sDE[l - 1][1]);
+    double kap = INFINITY;
+    double* dsh = sDE[l - 1][0];
+    double* esh = sDE[l - 1][1];
+    switch (l) {
+      case 1: kap = kappa_wave<3>(T, lane, dsh, esh); break;
+      case 2: kap = kappa_wave<5>(T, lane, dsh, esh); break;
+      case 3: kap = kappa_wave<7>(T, lane, dsh, esh); break;
+      case 4: kap = kappa_wave<9>(T, lane, dsh, esh); break;
+      case 5: kap = kappa_wave<11>(T, lane, dsh, esh); break;
+      case 6: kap = kappa_wave<13>(T, lane, dsh, esh); break;
+      case 7: kap = kappa_wave<15>(T, lane, dsh, esh); break;
+      case 8: kap = kappa_wave<17>(T, lane, dsh, esh); break;
+      case 9: kap = kappa_wave<19>(T, lane, dsh, esh); break;
+      case 10: kap = kappa_wave<21>(T, lane, dsh, esh); break;
+      case 11: kap = kappa_wave<23>(T, lane, dsh, esh); break;
+      case 12: kap = kappa_wave<25>(T, lane, dsh, esh); break;
+      case 13: kap = kappa_wave<27>(T, lane, dsh, esh); break;
+      case 14: kap = kappa_wave<29>(T, lane, dsh, esh); break;
+      case 15: kap = kappa_wave<31>(T, lane, dsh, esh); break;
+      default: kap = kappa_wave<33>(T, lane, dsh, esh); break;
+    }
     if (lane == 0) sKappa[l] = kap;
   }
   __syncthreads();

@@ -122,75 +122,110 @@ struct SrcP {
   }
 };
 
+// Coalesced value/column loads of the nonzeros [e0, e0+ne) of one row
+// block (ne <= CAP), thread t taking nonzeros t, t+NT, ...; indices are
+// clamped into the block so every load is unconditional.  Issued apart
+// from their use, so a kernel can fetch the next block while it works on
+// the current one.
+template <int NT, int CAP>
+struct RowFetch {
+  static constexpr int K = CAP / NT;
+  double a[K];
+  int32_t c[K];
+  __device__ __forceinline__ void issue(const int32_t* __restrict__ ci,
+                                        const double* __restrict__ va, int32_t e0, int32_t ne) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t e = t + NT * k;
+      const int32_t ee = e0 + (e < ne ? e : ne - 1);
+      a[k] = ldnt(va + ee);
+      c[k] = ldnt(ci + ee);
+    }
+  }
+};
+
+// Gathers src[c] for the fetched nonzeros and stores the products in LDS;
+// after a barrier the owner of each row adds its row's products in column
+// order (each product is rounded before the sum, as in a sequential CSR
+// product).
+template <int CH, int NT, int CAP, class S>
+__device__ __forceinline__ void fetched_rows(const RowFetch<NT, CAP>& f, const S& src,
+                                             int32_t ne, int32_t rs, int32_t re, bool own,
+                                             double* prod, double& sx, double& sy,
+                                             bool drain = false) {
+  constexpr int K = CAP / NT;
+  const int t = threadIdx.x;
+  sx = 0.0;
+  sy = 0.0;
+  if (ne > 0) {
+    double2 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = src.get(f.c[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t e = t + NT * k;
+      if (e < ne) {
+        if constexpr (CH == 2) {
+          prod[2 * e] = f.a[k] * v[k].x;
+          prod[2 * e + 1] = f.a[k] * v[k].y;
+        } else {
+          prod[e] = f.a[k] * v[k].x;
+        }
+      }
+    }
+  }
+  // with direct-to-LDS loads in flight, every wave waits for them before the
+  // barrier so their data is visible to the whole workgroup after it
+  if (drain) __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (own) {
+    for (int32_t e = rs; e < re; ++e) {
+      if constexpr (CH == 2) {
+        const double2 p = reinterpret_cast<const double2*>(prod)[e];
+        sx += p.x;
+        sy += p.y;
+      } else {
+        sx += prod[e];
+      }
+    }
+  }
+}
+
+// Row sums of a row longer than one block's nonzero capacity, reduced by
+// the whole workgroup (valid in thread 0).
+template <int CH, int NT, class S>
+__device__ __forceinline__ void long_row(const int32_t* __restrict__ ci,
+                                         const double* __restrict__ va, const S& src, int32_t e0,
+                                         int32_t ne, double* red, double& sx, double& sy) {
+  double px = 0.0, py = 0.0;
+  for (int32_t e = threadIdx.x; e < ne; e += NT) {
+    const double a = ldnt(va + e0 + e);
+    const double2 v = src.get(ldnt(ci + e0 + e));
+    px = fma(a, v.x, px);
+    py = fma(a, v.y, py);
+  }
+  px = block_sum<NT>(px, red);
+  if constexpr (CH == 2) py = block_sum<NT>(py, red);
+  sx = px;
+  sy = py;
+}
+
 // Row sums of one row block (rows r0.., nonzeros [e0, e0+ne)) for NT
-// threads.  When the block fits (ne <= SB_CAP) every thread first issues
-// all of its coalesced value/column loads (indices clamped into the block so
-// the loads are unconditional), then all of its gathers, and stores the
-// products in LDS; after a barrier the owner of each row (thread t, row
-// r0+t) adds its row's products in column order.  Each product is rounded
-// before the sum, as in a sequential CSR product.  A single row longer than
-// SB_CAP is reduced by the whole workgroup (valid in thread 0).
+// threads: fetch then products and row sums when the block fits (ne <=
+// CAP), else the single long row by the whole workgroup.
 template <int CH, int NT, int CAP, class S>
 __device__ __forceinline__ void stream_rows(const int32_t* __restrict__ ci,
                                             const double* __restrict__ va, const S& src,
                                             int32_t e0, int32_t ne, int32_t rs, int32_t re,
                                             bool own, double* prod, double* red, double& sx,
                                             double& sy) {
-  constexpr int K = CAP / NT;
-  const int t = threadIdx.x;
-  sx = 0.0;
-  sy = 0.0;
   if (ne <= CAP) {
-    if (ne > 0) {
-      double a[K];
-      int32_t c[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int32_t e = t + NT * k;
-        const int32_t ee = e0 + (e < ne ? e : ne - 1);
-        a[k] = ldnt(va + ee);
-        c[k] = ldnt(ci + ee);
-      }
-      double2 v[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = src.get(c[k]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int32_t e = t + NT * k;
-        if (e < ne) {
-          if constexpr (CH == 2) {
-            prod[2 * e] = a[k] * v[k].x;
-            prod[2 * e + 1] = a[k] * v[k].y;
-          } else {
-            prod[e] = a[k] * v[k].x;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (own) {
-      for (int32_t e = rs; e < re; ++e) {
-        if constexpr (CH == 2) {
-          const double2 p = reinterpret_cast<const double2*>(prod)[e];
-          sx += p.x;
-          sy += p.y;
-        } else {
-          sx += prod[e];
-        }
-      }
-    }
+    RowFetch<NT, CAP> f;
+    if (ne > 0) f.issue(ci, va, e0, ne);
+    fetched_rows<CH, NT, CAP>(f, src, ne, rs, re, own, prod, sx, sy);
   } else {
-    double px = 0.0, py = 0.0;
-    for (int32_t e = t; e < ne; e += NT) {
-      const double a = ldnt(va + e0 + e);
-      const double2 v = src.get(ldnt(ci + e0 + e));
-      px = fma(a, v.x, px);
-      py = fma(a, v.y, py);
-    }
-    px = block_sum<NT>(px, red);
-    if constexpr (CH == 2) py = block_sum<NT>(py, red);
-    sx = px;
-    sy = py;
+    long_row<CH, NT>(ci, va, src, e0, ne, red, sx, sy);
   }
 }
 

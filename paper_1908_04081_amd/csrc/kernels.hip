@@ -179,11 +179,17 @@ void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, do
 }
 
 // --------------------------------- last level fused with the Gram partials
-// For each row block (<= 256 rows): stage Y's 2 sbar columns in LDS
-// (column-major, 256-row stride, rows past the block zero), compute P_sbar
-// for the block (CSR-stream; its theta/mu terms read the staged columns),
-// then every wave adds its share of the unique products Y_a * Y_b of the
-// block's rows to register accumulators.  Columns past 2 sbar + 1 stay zero.
+// Zero source of the direct-to-LDS basis loads for rows past a block.
+__device__ double2 g_zero_rows[64];
+
+// For each row block (<= 256 rows): the block's s-bar basis pairs go from
+// HBM straight into a pair-major LDS tile (direct-to-LDS loads, no
+// registers), the CSR-stream products give P_sbar for the block's rows
+// (stored as the tile's level s-bar), then every wave adds its share of the
+// unique products Y_a * Y_b over the tile's rows to register accumulators.
+// The next block's nonzeros are fetched before the Gram products, so their
+// HBM latency overlaps them.  Rows past the block and columns past
+// 2 sbar + 1 are zero.
 template <int NC, int W>
 __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctl, CsrView A,
                                                       const double2* __restrict__ pairs,
@@ -193,7 +199,8 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   constexpr int NT = 64 * W;
   constexpr int QMAX = GramPlanHolder<NC, W>::QMAX;
   constexpr int TS = SB_ROWS;
-  __shared__ double tile[NC * TS];
+  constexpr int NL = (NC + 1) / 2;   // pair levels of the tile (the last one holds P_sbar, 0)
+  __shared__ double2 tile[NL * TS];
   __shared__ double prod[SB_CAP];
   __shared__ double red[W];
   const int s = ctl->sbar;
@@ -202,96 +209,56 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   const double mu = (s >= 2) ? ctl->mu[s - 2] : 0.0;
   const double* __restrict__ xsrc = reinterpret_cast<const double*>(pairs + (size_t)(s - 1) * ld);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < (NC - 2 * s - 1) * TS; i += NT) tile[(2 * s + 1) * TS + i] = 0.0;
+  for (int i = (s + 1) * TS + tid; i < NL * TS; i += NT) tile[i] = make_double2(0.0, 0.0);
   double acc[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) acc[q] = 0.0;
 
-  // Basis rows of the next block are loaded into registers while the Gram
-  // products of the current block run (software pipelining), where the
-  // register budget allows it (up to 21 columns); otherwise per block.
-  constexpr bool PREFETCH = NC <= 21;
-  constexpr int PF = ((NC - 1) / 2 * TS + NT - 1) / NT;
-  double2 pf[PF];
-  auto load_pairs = [&](int32_t b) {
-    const int32_t r0 = A.blk[b], nr = A.blk[b + 1] - r0;
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int i = tid + NT * k;
-      const int l = i / TS, rl = i % TS;
-      pf[k] = (l < s && rl < nr) ? pairs[(size_t)l * ld + r0 + rl] : make_double2(0.0, 0.0);
-    }
-  };
   int32_t b0, b1;
   block_range(A.nblk, b0, b1);
-  if (PREFETCH && b0 < b1) load_pairs(b0);
+  RowFetch<NT, SB_CAP> f;
+  BlockRows br(A, b0 < b1 ? b0 : 0);
+  if (b0 < b1 && br.ne <= SB_CAP && br.ne > 0) f.issue(A.ci, A.va, br.e0, br.ne);
   for (int32_t b = b0; b < b1; ++b) {
-    if (!PREFETCH) load_pairs(b);
-    const BlockRows br(A, b);
-    // stage the 2 s basis columns of the block's rows (zero past the block)
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int i = tid + NT * k;
-      const int l = i / TS, rl = i % TS;
-      if (l < s) {
-        tile[(2 * l) * TS + rl] = pf[k].x;
-        tile[(2 * l + 1) * TS + rl] = pf[k].y;
-      }
+    // basis pairs of the block's rows: 64-row chunks, one load per chunk and
+    // wave instruction; lanes past the block read zeros
+    const int32_t r0 = br.r0, nr = br.nr;
+    for (int i = wave; i < 4 * s; i += W) {
+      const int l = i >> 2, row = ((i & 3) << 6) + lane;
+      const double2* src = (row < nr) ? pairs + (size_t)l * ld + r0 + row : g_zero_rows + lane;
+      __builtin_amdgcn_global_load_lds(
+          (const void*)src,
+          (void __attribute__((address_space(3)))*)(tile + l * TS + ((i & 3) << 6)), 16, 0, 0);
     }
     double a, unused;
-    stream_rows<1, NT, SB_CAP>(A.ci, A.va, SrcP{xsrc}, br.e0, br.ne, br.rs, br.re, br.own, prod,
-                               red, a, unused);
+    if (br.ne <= SB_CAP) {
+      fetched_rows<1, NT, SB_CAP>(f, SrcP{xsrc}, br.ne, br.rs, br.re, br.own, prod, a, unused,
+                                  true);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);
+      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, br.e0, br.ne, red, a, unused);
+    }
+    // tile complete (every wave waited for its loads before the barrier)
     if (tid < TS) {
       double y = 0.0;
       if (br.own) {
-        y = a - th * tile[(2 * s - 2) * TS + tid];
-        if (mu != 0.0) y -= mu * tile[(2 * s - 4) * TS + tid];
+        y = a - th * tile[(s - 1) * TS + tid].x;
+        if (mu != 0.0) y -= mu * tile[(s - 2) * TS + tid].x;
         y = y / ga;
         plast[br.row] = y;
       }
-      tile[(2 * s) * TS + tid] = y;
+      tile[s * TS + tid] = make_double2(y, 0.0);
+    }
+    const int nsub = (nr + 63) >> 6;
+    if (b + 1 < b1) {
+      br = BlockRows(A, b + 1);
+      if (br.ne <= SB_CAP && br.ne > 0) f.issue(A.ci, A.va, br.e0, br.ne);
     }
     __syncthreads();
-    if (PREFETCH && b + 1 < b1) load_pairs(b + 1);
-    const int nsub = (br.nr + 63) >> 6;
-    for (int q = 0; q < nsub; ++q) {
-      const double* tq = tile + q * 64;
-      switch (wave) {
-        case 0: gram_accum_wave<NC, W, 0, TS>(acc, tq, lane); break;
-        case 1: gram_accum_wave<NC, W, 1, TS>(acc, tq, lane); break;
-        case 2: gram_accum_wave<NC, W, 2, TS>(acc, tq, lane); break;
-        case 3: gram_accum_wave<NC, W, 3, TS>(acc, tq, lane); break;
-        default:
-          if constexpr (W > 4) {
-            switch (wave) {
-              case 4: gram_accum_wave<NC, W, (W > 4 ? 4 : 0), TS>(acc, tq, lane); break;
-              case 5: gram_accum_wave<NC, W, (W > 5 ? 5 : 0), TS>(acc, tq, lane); break;
-              case 6: gram_accum_wave<NC, W, (W > 6 ? 6 : 0), TS>(acc, tq, lane); break;
-              case 7: gram_accum_wave<NC, W, (W > 7 ? 7 : 0), TS>(acc, tq, lane); break;
-            }
-          }
-          break;
-      }
-    }
+    for (int q = 0; q < nsub; ++q) gram_accum<NC, W, TS>(wave, acc, tile + q * 64, lane);
     __syncthreads();
   }
-  const auto qs = std::make_integer_sequence<int, QMAX>{};
-  switch (wave) {
-    case 0: gram_flush<NC, W, 0>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-    case 1: gram_flush<NC, W, 1>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-    case 2: gram_flush<NC, W, 2>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-    case 3: gram_flush<NC, W, 3>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-    default:
-      if constexpr (W > 4) {
-        switch (wave) {
-          case 4: gram_flush<NC, W, (W > 4 ? 4 : 0)>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-          case 5: gram_flush<NC, W, (W > 5 ? 5 : 0)>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-          case 6: gram_flush<NC, W, (W > 6 ? 6 : 0)>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-          case 7: gram_flush<NC, W, (W > 7 ? 7 : 0)>(acc, lane, partials, gridDim.x, blockIdx.x, qs); break;
-        }
-      }
-      break;
-  }
+  gram_flush_all<NC, W>(wave, acc, lane, partials, gridDim.x, blockIdx.x);
 }
 
 template <int NC>
