@@ -207,10 +207,11 @@ assg_status_t assg_basis_params(int32_t kind, double lmin, double lmax, int32_t 
  * reduction partials).  Host only. */
 assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes);
 
-/* Prepares A for the kernels: reads row_ptr once (device -> host), picks the
- * lanes-per-row width of the CSR kernels from the longest row, and sizes
- * launches.  Must be called again when the sparsity pattern changes;
- * values may change freely between solves. */
+/* Prepares A for the kernels: reads row_ptr once (device -> host) and cuts
+ * the rows into the row blocks of the CSR-stream kernels (at most 256 rows
+ * and 2048 nonzeros each; a longer row is a block of its own).  Must be
+ * called again when the sparsity pattern changes; values may change freely
+ * between solves. */
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
 
 /* ------------------------------------------------------------- the solves */
@@ -237,6 +238,19 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
  * memory: at most cap records, *count = records available. */
 assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t cap,
                              int64_t* count);
+
+/* ------------------------------------------------------- differentiation */
+
+/* out[k] = alpha * u[row(k)] * v[col(k)] for every stored nonzero k of A:
+ * the entries of alpha u v^T on A's sparsity pattern.  With x = A^{-1} b and
+ * a loss L(x), the adjoint solution lambda = A^{-1} dL/dx (A is symmetric, so
+ * the adjoint system has the same matrix) gives dL/db = lambda and
+ * dL/dA_ij = -lambda_i x_j; with alpha = -1, u = lambda, v = x this call
+ * writes the gradient with respect to A's stored values (every stored entry
+ * counted as its own variable).  u, v (device, n), out (device, nnz; may not
+ * alias u or v).  Returns after the kernel has completed. */
+assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, const double* u,
+                                        const double* v, double alpha, double* out);
 
 /* ------------------------------------------ single steps of the hot path */
 

@@ -118,6 +118,7 @@ def lib():
                                   C.POINTER(AssgInfo)]),
         "assg_get_trace": (I32, [P, C.POINTER(AssgTrace), I64, C.POINTER(C.c_int64)]),
         "assg_spmv": (I32, [P, C.POINTER(AssgCsr), P, P]),
+        "assg_csr_outer_on_pattern": (I32, [P, C.POINTER(AssgCsr), P, P, D, P]),
         "assg_basis_gram": (I32, [P, C.POINTER(AssgCsr), P, P, I32, C.POINTER(D), C.POINTER(D),
                                   C.POINTER(D), P, C.POINTER(D)]),
         "assg_block_controller": (I32, [P, C.POINTER(D), I32, D, D, I32, I32,
@@ -296,6 +297,13 @@ def assg_get_trace(h: Handle) -> list:
 def assg_spmv(h: Handle, A: DeviceCSR, x, y):
     d = A.c()
     _check(lib().assg_spmv(h.ptr, C.byref(d), _dptr(x), _dptr(y)), h.ptr)
+
+
+def assg_csr_outer_on_pattern(h: Handle, A: DeviceCSR, u, v, alpha: float, out):
+    """out[k] = alpha * u[row(k)] * v[col(k)] on A's pattern (CUDA float64)."""
+    d = A.c()
+    _check(lib().assg_csr_outer_on_pattern(h.ptr, C.byref(d), _dptr(u), _dptr(v), float(alpha),
+                                           _dptr(out)), h.ptr)
 
 
 def assg_basis_gram(h: Handle, A: DeviceCSR, p, r, s: int, theta, gamma, mu, Y_out=None):

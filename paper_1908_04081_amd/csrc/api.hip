@@ -381,6 +381,20 @@ assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, d
   return ASSG_OK;
 }
 
+assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, const double* u,
+                                        const double* v, double alpha, double* out) {
+  if (!h || !u || !v || !out) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  assg_status_t st = check_analyzed(h, A);
+  if (st != ASSG_OK) return st;
+  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  launch_outer_pattern(h->stream, Av, u, v, alpha, out);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return ASSG_OK;
+}
+
 static assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o) {
   if (!o) return fail(h, ASSG_ERR_INVALID_ARG, "null options");
   if (o->s_max < 1 || o->s_max > ASSG_MAX_S)

@@ -642,6 +642,43 @@ void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, doubl
 }
 
 // ----------------------------------------------------- basis/Gram helpers
+// ------------------------------------------- differentiation: alpha u v^T
+// One row block per workgroup: the owner of each row writes its (local) row
+// number for the row's nonzeros into LDS, then the nonzeros are visited in
+// order with coalesced column loads and stores.
+__global__ __launch_bounds__(256) void k_outer_pattern(CsrView A, const double* __restrict__ u,
+                                                       const double* __restrict__ v, double alpha,
+                                                       double* __restrict__ out) {
+  __shared__ uint8_t rowof[SB_CAP];
+  __shared__ double su[SB_ROWS];
+  int32_t b0, b1;
+  block_range(A.nblk, b0, b1);
+  for (int32_t b = b0; b < b1; ++b) {
+    const BlockRows br(A, b);
+    const int t = threadIdx.x;
+    if (br.ne <= SB_CAP) {
+      if (br.own) {
+        su[t] = alpha * u[br.row];
+        for (int32_t e = br.rs; e < br.re; ++e) rowof[e] = (uint8_t)t;
+      }
+      __syncthreads();
+      for (int32_t e = t; e < br.ne; e += 256)
+        out[br.e0 + e] = su[rowof[e]] * v[A.ci[br.e0 + e]];
+    } else {
+      const double ui = alpha * u[br.r0];
+      for (int32_t e = t; e < br.ne; e += 256)
+        out[br.e0 + e] = ui * v[A.ci[br.e0 + e]];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
+                          double alpha, double* out) {
+  hipLaunchKernelGGL(k_outer_pattern, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, A, u, v,
+                     alpha, out);
+}
+
 __global__ void k_pair_init(int64_t n, const double* __restrict__ p, const double* __restrict__ r,
                             double2* __restrict__ pairs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -73,6 +73,10 @@ void launch_h_dir(hipStream_t s, const Ctl* ctl, const CsrView& A, const double*
 void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, double* r,
                      const double* p, const double* w, double* part);
 
+// out[k] = alpha u[row(k)] v[col(k)] on A's pattern.
+void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
+                          double alpha, double* out);
+
 // Helpers of assg_basis_gram.
 void launch_pair_init(hipStream_t s, int64_t n, const double* p, const double* r, double2* pairs);
 void launch_export_Y(hipStream_t s, int64_t n, int sbar, const double2* pairs,

@@ -267,3 +267,22 @@ def make_config(name: str, size: int | None = None) -> Problem:
     else:
         raise KeyError(name)
     return Problem(name=name, A=A, b=b, x0=np.zeros(A.shape[0]), xstar=xs)
+
+
+def transpose_index(A: sp.csr_matrix) -> np.ndarray:
+    """For a CSR matrix with a symmetric pattern: t[k] = position of the
+    entry (j, i) for the stored entry k = (i, j)."""
+    A = A.tocsr()
+    P = sp.csr_matrix((np.arange(A.nnz, dtype=np.float64), A.indices, A.indptr), shape=A.shape)
+    T = P.T.tocsr()
+    T.sort_indices()
+    if not (np.array_equal(T.indptr, A.indptr) and np.array_equal(T.indices, A.indices)):
+        raise ValueError("pattern is not symmetric")
+    return T.data.astype(np.int64)
+
+
+def symmetric_direction(A: sp.csr_matrix, seed: int) -> np.ndarray:
+    """A random direction in the stored values of A that keeps A symmetric:
+    d_k = z_k + z_t(k), z ~ N(0, 1)."""
+    z = _rng(seed).standard_normal(A.nnz)
+    return z + z[transpose_index(A)]
