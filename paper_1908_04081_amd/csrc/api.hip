@@ -35,6 +35,8 @@ struct assg_handle_s {
   int32_t* d_blk = nullptr;      // row-block partition (row starts, nonzero starts)
   int32_t* d_blke = nullptr;
   int32_t nblk = 0;
+  int32_t* d_chunks = nullptr;   // chunk starts (nchunk + 1) then system chunk starts (2)
+  int32_t nchunk = 0;
   double* d_part = nullptr;      // per-workgroup partial sums (sized at analyze)
   int gram_blocks[MAXS + 1] = {0};
   double leja[MAXS];
@@ -198,10 +200,24 @@ bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_sta
 
 // Workgroups of the persistent last-sweep + Gram kernel: the occupancy
 // limit over all CUs, but no more than row blocks (rounded up to 8).
-int gram_grid(assg_handle_t h, int sigma) {
-  const int occ = h->gram_blocks[sigma];
-  const int nb8 = (h->nblk + 7) / 8 * 8;
-  return std::max(8, std::min(occ, nb8));
+// The kernels' view of the analyzed single matrix (a batch of one).
+CsrView view(assg_handle_t h, const assg_csr_t* A) {
+  CsrView v{};
+  v.n = A->n;
+  v.nnz = A->nnz;
+  v.rp = A->row_ptr;
+  v.ci = A->col_idx;
+  v.va = A->val;
+  v.blk = h->d_blk;
+  v.blke = h->d_blke;
+  v.nblk = h->nblk;
+  v.bsys = nullptr;
+  v.cblk = h->d_chunks;
+  v.csys = nullptr;
+  v.sys_chunk = h->d_chunks + h->nchunk + 1;
+  v.nchunk = h->nchunk;
+  v.nsys = 1;
+  return v;
 }
 
 hipEvent_t pool_event(assg_handle_t h, size_t i) {
@@ -312,6 +328,7 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_trace) (void)hipFree(h->d_trace);
   if (h->d_blk) (void)hipFree(h->d_blk);
   if (h->d_blke) (void)hipFree(h->d_blke);
+  if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -358,9 +375,22 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_blke, blke.data(), blke.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, h->stream));
   h->nblk = (int32_t)(blk.size() - 1);
+  {
+    std::vector<int32_t> cblk, csys, sys_chunk, sys_blk{0, h->nblk};
+    make_chunks(sys_blk, h->gram_blocks[10], cblk, csys, sys_chunk);
+    if (h->d_chunks) HIP_OR_FAIL(h, hipFree(h->d_chunks));
+    h->d_chunks = nullptr;
+    std::vector<int32_t> tab(cblk);
+    tab.insert(tab.end(), sys_chunk.begin(), sys_chunk.end());
+    HIP_OR_FAIL(h, hipMalloc(&h->d_chunks, tab.size() * sizeof(int32_t)));
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_chunks, tab.data(), tab.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, h->stream));
+    h->nchunk = (int32_t)cblk.size() - 1;
+  }
   if (h->d_part) HIP_OR_FAIL(h, hipFree(h->d_part));
   h->d_part = nullptr;
   HIP_OR_FAIL(h, hipMalloc(&h->d_part, reduce_doubles(h->nblk) * sizeof(double)));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));   // host tables above go out of scope
   h->an_n = A->n;
   h->an_nnz = A->nnz;
   h->an_rp = A->row_ptr;
@@ -372,7 +402,7 @@ assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, d
   if (!h || !x || !y) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
-  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  const CsrView Av = view(h, A);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   launch_spmv(h->stream, Av, x, y);
@@ -386,7 +416,7 @@ assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, co
   if (!h || !u || !v || !out) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
-  const CsrView Av{A->n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  const CsrView Av = view(h, A);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   launch_outer_pattern(h->stream, Av, u, v, alpha, out);
@@ -443,8 +473,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
       h->trace_cap = cap;
     }
   }
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
-  const int nbg = gram_grid(h, sigma);
+  const CsrView Av = view(h, A);
 
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 0);
@@ -494,10 +523,10 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
         timed.push_back({enqueued, 2, evn});
         HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
       }
-      launch_last_gram(h->stream, h->d_ctl, sigma, Av, nbg, pairs, plast, lay.ld, grampart);
+      launch_last_gram(h->stream, h->d_ctl, sigma, Av, pairs, plast, lay.ld, grampart);
       if (timing) HIP_OR_FAIL(h, hipEventRecord(pool_event(h, evn++), h->stream));
-      launch_gram_reduce(h->stream, h->d_ctl, sigma, nbg, grampart);
-      launch_controller(h->stream, h->d_ctl, h->d_trace, sigma);
+      launch_gram_reduce(h->stream, h->d_ctl, sigma, Av, grampart);
+      launch_controller(h->stream, h->d_ctl, h->d_trace, sigma, 1);
       launch_recover(h->stream, h->d_ctl, Av, pairs, plast, lay.ld, x);
       launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, h->d_part, 0);
     }
@@ -582,7 +611,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   double* r = reinterpret_cast<double*>(base);
   double* p = r + lay.ld;
   double* w = r + 2 * lay.ld;
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  const CsrView Av = view(h, A);
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 1);
   c->tol = tol;
@@ -651,7 +680,7 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   double2* pairs = reinterpret_cast<double2*>(base + lay.pairs_off);
   double* plast = reinterpret_cast<double*>(base + lay.plast_off);
   double* grampart = reinterpret_cast<double*>(base + lay.grampart_off);
-  const CsrView Av{n, A->nnz, A->row_ptr, A->col_idx, A->val, h->d_blk, h->d_blke, h->nblk};
+  const CsrView Av = view(h, A);
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 0);
   c->sbar = s;
@@ -666,9 +695,8 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   launch_pair_init(h->stream, n, p, r, pairs);
   for (int l = 1; l < s; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
-  const int nbg = gram_grid(h, s);
-  launch_last_gram(h->stream, h->d_ctl, s, Av, nbg, pairs, plast, lay.ld, grampart);
-  launch_gram_reduce(h->stream, h->d_ctl, s, nbg, grampart);
+  launch_last_gram(h->stream, h->d_ctl, s, Av, pairs, plast, lay.ld, grampart);
+  launch_gram_reduce(h->stream, h->d_ctl, s, Av, grampart);
   if (Y_out) launch_export_Y(h->stream, n, s, pairs, plast, lay.ld, Y_out);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
@@ -726,7 +754,7 @@ assg_status_t assg_block_controller(assg_handle_t h, const double* G, int32_t sb
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
-  launch_controller(h->stream, h->d_ctl, nullptr, s_max);
+  launch_controller(h->stream, h->d_ctl, nullptr, s_max, 1);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipMemcpyAsync(c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));

@@ -170,8 +170,9 @@ __device__ __forceinline__ double gmv(const double* grow, double v) {
 
 constexpr int CTL_WAVES = 8;   // wave w estimates blocks w+1, w+9 (256 VGPRs per lane)
 
-__global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__ ctl,
+__global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__ ctls,
                                                      assg_trace_t* __restrict__ trace) {
+  Ctl* __restrict__ ctl = ctls + blockIdx.x;   // one workgroup per system
   if (ctl->status != ST_RUNNING) return;
   __shared__ double sG[MAXC * MAXC];
   __shared__ double sScr[SCRATCH_ROWS * MAXC];
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
     ctl->rho_m = rho_m;
     ctl->phi = phi;
     ctl->relres_upd = sqrt(rGr) / nb;
-    if (ctl->record_trace && k < ctl->trace_cap) {
+    if (trace && ctl->record_trace && k < ctl->trace_cap) {
       assg_trace_t& tr = trace[k];
       tr.k = (int32_t)k;
       tr.sbar = sbar;
@@ -394,9 +395,10 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   }
 }
 
-void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma) {
+void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma, int nsys) {
   const int waves = sigma < 1 ? 1 : (sigma < CTL_WAVES ? sigma : CTL_WAVES);
-  hipLaunchKernelGGL(k_controller, dim3(1), dim3(64 * waves), 0, s, ctl, trace);
+  hipLaunchKernelGGL(k_controller, dim3(nsys), dim3(64 * waves), 0, s, ctl,
+                     nsys == 1 ? trace : nullptr);
 }
 
 }  // namespace assg

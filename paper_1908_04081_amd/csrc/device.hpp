@@ -237,6 +237,21 @@ __device__ __forceinline__ void block_range(int32_t nblk, int32_t& b0, int32_t& 
   b1 = (int32_t)(((int64_t)nblk * (L + 1)) / gridDim.x);
 }
 
+// Chunk of a reduction kernel's workgroup (XCD-aware, one chunk per
+// workgroup; the grid is nchunk) and its row blocks [b0, b1) and system.
+template <class V>
+__device__ __forceinline__ int32_t chunk_of(const V& A, int32_t& b0, int32_t& b1, int32_t& sys) {
+  const int32_t c = xcd_logical(blockIdx.x, gridDim.x);
+  b0 = A.cblk[c];
+  b1 = A.cblk[c + 1];
+  sys = A.csys ? A.csys[c] : 0;
+  return c;
+}
+template <class V>
+__device__ __forceinline__ int32_t block_sys(const V& A, int32_t b) {
+  return A.bsys ? A.bsys[b] : 0;
+}
+
 // ------------------------------------------------------ grid reductions
 // Grid kernels store one partial per workgroup (plain stores; the next
 // kernel sees them at the kernel boundary, so no cross-workgroup fences are

@@ -22,17 +22,42 @@
 namespace assg {
 
 
-void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk) {
+void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk, int rows, int cap) {
   blk.clear();
   blk.push_back(0);
   int64_t r = 0;
   while (r < n) {
     const int64_t r0 = r;
     ++r;                                    // a block always takes its first row
-    if ((int64_t)rp[r] - rp[r0] <= SB_CAP)
-      while (r < n && r - r0 < SB_ROWS && (int64_t)rp[r + 1] - rp[r0] <= SB_CAP) ++r;
+    if ((int64_t)rp[r] - rp[r0] <= cap)
+      while (r < n && r - r0 < rows && (int64_t)rp[r + 1] - rp[r0] <= cap) ++r;
     blk.push_back((int32_t)r);
   }
+}
+
+void make_chunks(const std::vector<int32_t>& sys_blk, int target, std::vector<int32_t>& cblk,
+                 std::vector<int32_t>& csys, std::vector<int32_t>& sys_chunk) {
+  const int nsys = (int)sys_blk.size() - 1;
+  const int64_t nblk = sys_blk[nsys];
+  cblk.clear();
+  csys.clear();
+  sys_chunk.assign(1, 0);
+  for (int i = 0; i < nsys; ++i) {
+    const int64_t b0 = sys_blk[i], nb = sys_blk[i + 1] - b0;
+    int64_t k = (nblk > 0) ? (nb * target + nblk / 2) / nblk : 1;
+    if (k < 1) k = 1;
+    if (k > nb && nb > 0) k = nb;
+    for (int64_t c = 0; c < k; ++c) {
+      cblk.push_back((int32_t)(b0 + nb * c / k));
+      csys.push_back(i);
+    }
+    sys_chunk.push_back((int32_t)cblk.size());
+  }
+  while (cblk.size() % NXCD) {
+    cblk.push_back((int32_t)nblk);
+    csys.push_back(nsys - 1);
+  }
+  cblk.push_back((int32_t)nblk);
 }
 
 size_t reduce_doubles(int32_t nblk) {
@@ -93,15 +118,18 @@ void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y) {
 }
 
 // ----------------------------------------------------------------- setup
+// One chunk of row blocks per workgroup (chunks never straddle systems);
+// the partial ||b||^2 of each chunk, summed per system by k_fin_setup.
 __global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CsrView A, const double* __restrict__ b,
                                                const double* __restrict__ x,
                                                double2* __restrict__ pairs,
                                                double* __restrict__ part) {
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
-  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  int32_t b0, b1, sys;
+  const int32_t c = chunk_of(A, b0, b1, sys);
   double my = 0.0;
-  if (bb < A.nblk) {
+  for (int32_t bb = b0; bb < b1; ++bb) {
     const BlockRows br(A, bb);
     double bi = 0.0;
     if (br.own) bi = b[br.row];
@@ -111,45 +139,49 @@ __global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CsrView A, const double
     if (br.own) {
       const double ri = bi - ax;
       pairs[br.row] = make_double2(ri, ri);
-      my = bi * bi;
+      my = fma(bi, bi, my);
     }
+    __syncthreads();
   }
   my = block_sum<256>(my, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = my;
+  if (threadIdx.x == 0) part[c] = my;
 }
 
-__global__ __launch_bounds__(1024) void k_fin_setup(Ctl* ctl, const double* __restrict__ part,
-                                                    int n) {
+// System blockIdx.x: the sum of its chunks' partials, in chunk order.
+__global__ __launch_bounds__(1024) void k_fin_setup(Ctl* ctl, CsrView A,
+                                                    const double* __restrict__ part) {
   __shared__ double sh[16];
-  const double t = finish_sum<1024>(part, n, sh);
-  if (threadIdx.x == 0) ctl->nb = sqrt(t);
+  const int i = blockIdx.x;
+  const int32_t c0 = A.sys_chunk[i], c1 = A.sys_chunk[i + 1];
+  const double t = finish_sum<1024>(part + c0, c1 - c0, sh);
+  if (threadIdx.x == 0) ctl[i].nb = sqrt(t);
 }
 
 void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
                   double2* pairs, double* part) {
-  const int g = block_grid(A, 1 << 30);
-  hipLaunchKernelGGL(k_setup, dim3(g), dim3(256), 0, s, ctl, A, b, x, pairs, part);
-  hipLaunchKernelGGL(k_fin_setup, dim3(1), dim3(1024), 0, s, ctl, part, g);
+  hipLaunchKernelGGL(k_setup, dim3(A.nchunk), dim3(256), 0, s, ctl, A, b, x, pairs, part);
+  hipLaunchKernelGGL(k_fin_setup, dim3(A.nsys), dim3(1024), 0, s, ctl, A, part);
 }
 
 // ------------------------------------------------ matrix powers: one level
 // y_l = (A y_{l-1} - theta_{l-1} y_{l-1} - mu_{l-2} y_{l-2}) / gamma_{l-1}
 // for both chains (2.3) from one read of A and one 16-byte gather per
 // nonzero; levels beyond the loop's s-bar exit at once.
-__global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctl, int level, CsrView A,
+__global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int level, CsrView A,
                                                double2* __restrict__ pairs, int64_t ld) {
-  if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
   __shared__ double prod[2 * SB_CAP];
   __shared__ double red[4];
-  const double th = ctl->theta[level - 1];
-  const double ga = ctl->gamma[level - 1];
-  const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
   const double2* __restrict__ X = pairs + (size_t)(level - 1) * ld;
   const double2* __restrict__ X2 = pairs + (size_t)(level >= 2 ? level - 2 : 0) * ld;
   double2* __restrict__ Yo = pairs + (size_t)level * ld;
   int32_t b0, b1;
   block_range(A.nblk, b0, b1);
   for (int32_t b = b0; b < b1; ++b) {
+    const Ctl* ctl = ctls + block_sys(A, b);
+    if (ctl->status != ST_RUNNING || level >= ctl->sbar) continue;
+    const double th = ctl->theta[level - 1];
+    const double ga = ctl->gamma[level - 1];
+    const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
     const BlockRows br(A, b);
     double2 xo = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
     if (br.own) {
@@ -191,10 +223,13 @@ __device__ double2 g_zero_rows[64];
 // HBM latency overlaps them.  Rows past the block and columns past
 // 2 sbar + 1 are zero.
 template <int NC, int W>
-__global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctl, CsrView A,
+__global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctls, CsrView A,
                                                       const double2* __restrict__ pairs,
                                                       double* __restrict__ plast, int64_t ld,
                                                       double* __restrict__ partials) {
+  int32_t b0, b1, sys;
+  const int32_t chunk = chunk_of(A, b0, b1, sys);
+  const Ctl* ctl = ctls + sys;
   if (ctl->status != ST_RUNNING) return;
   constexpr int NT = 64 * W;
   constexpr int QMAX = GramPlanHolder<NC, W>::QMAX;
@@ -214,8 +249,6 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) acc[q] = 0.0;
 
-  int32_t b0, b1;
-  block_range(A.nblk, b0, b1);
   RowFetch<NT, SB_CAP> f;
   BlockRows br(A, b0 < b1 ? b0 : 0);
   if (b0 < b1 && br.ne <= SB_CAP && br.ne > 0) f.issue(A.ci, A.va, br.e0, br.ne);
@@ -258,7 +291,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
     for (int q = 0; q < nsub; ++q) gram_accum<NC, W, TS>(wave, acc, tile + q * 64, lane);
     __syncthreads();
   }
-  gram_flush_all<NC, W>(wave, acc, lane, partials, gridDim.x, blockIdx.x);
+  gram_flush_all<NC, W>(wave, acc, lane, partials, A.nchunk, chunk);
 }
 
 template <int NC>
@@ -303,24 +336,28 @@ int last_gram_blocks(int sigma, int cus) {
   return nb;
 }
 
-void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int nblocks,
+void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A,
                       const double2* pairs, double* plast, int64_t ld, double* partials) {
   ASSG_SIGMA_SWITCH(sigma, {
     constexpr int W = gram_waves<NC>();
-    hipLaunchKernelGGL((k_last_gram<NC, W>), dim3(nblocks), dim3(64 * W), 0, s, ctl, A, pairs,
+    hipLaunchKernelGGL((k_last_gram<NC, W>), dim3(A.nchunk), dim3(64 * W), 0, s, ctl, A, pairs,
                        plast, ld, partials);
   });
 }
 
-// G[a][b] = G[b][a] = sum over workgroups of the partials, fixed order.
+// G[a][b] = G[b][a] of system blockIdx.y = the sum of its chunks' partials
+// of entry blockIdx.x, fixed order.
 template <int NC>
-__global__ __launch_bounds__(256) void k_gram_reduce(Ctl* __restrict__ ctl, int nparts,
+__global__ __launch_bounds__(256) void k_gram_reduce(Ctl* __restrict__ ctls, CsrView A,
                                                      const double* __restrict__ partials) {
+  Ctl* ctl = ctls + blockIdx.y;
   if (ctl->status != ST_RUNNING) return;
   __shared__ double sh[4];
   const int p = blockIdx.x;
+  const int32_t c0 = A.sys_chunk[blockIdx.y], c1 = A.sys_chunk[blockIdx.y + 1];
+  const double* __restrict__ src = partials + (size_t)p * A.nchunk;
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) s += partials[(size_t)p * nparts + i];
+  for (int32_t i = c0 + threadIdx.x; i < c1; i += 256) s += src[i];
   s = block_sum<256>(s, sh);
   if (threadIdx.x == 0) {
     int a = 0, q = p;
@@ -334,9 +371,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce(Ctl* __restrict__ ctl, int 
   }
 }
 
-void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const double* partials) {
-  ASSG_SIGMA_SWITCH(sigma, hipLaunchKernelGGL(k_gram_reduce<NC>, dim3(NC * (NC + 1) / 2),
-                                              dim3(256), 0, s, ctl, nparts, partials));
+void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, const CsrView& A,
+                        const double* partials) {
+  ASSG_SIGMA_SWITCH(sigma, hipLaunchKernelGGL(k_gram_reduce<NC>, dim3(NC * (NC + 1) / 2, A.nsys),
+                                              dim3(256), 0, s, ctl, A, partials));
 }
 
 // -------------------------------------------------------------- recovery
@@ -345,13 +383,14 @@ void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const do
 // (p, r) overwrite basis level 0 row by row (each row is read before it is
 // written by the same thread).  One workgroup per row block, one row per
 // thread, all basis loads of a row issued together.
-__global__ __launch_bounds__(256) void k_recover(const Ctl* __restrict__ ctl, CsrView A,
+__global__ __launch_bounds__(256) void k_recover(const Ctl* __restrict__ ctls, CsrView A,
                                                  double2* __restrict__ pairs,
                                                  const double* __restrict__ plast, int64_t ld,
                                                  double* __restrict__ x) {
-  if (ctl->status != ST_RUNNING || ctl->skip_recover) return;
   const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
   if (bb >= A.nblk) return;
+  const Ctl* ctl = ctls + block_sys(A, bb);
+  if (ctl->status != ST_RUNNING || ctl->skip_recover) return;
   const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
   if ((int)threadIdx.x >= nr) return;
   const int64_t row = (int64_t)r0 + threadIdx.x;
@@ -393,7 +432,7 @@ __device__ void commit_loop(Ctl* ctl, assg_trace_t* trace, bool checked, double 
   const int64_t k = ctl->k;
   if (checked) {
     ctl->relres_true = rel;
-    if (ctl->record_trace && k < ctl->trace_cap) trace[k].relres_true = rel;
+    if (trace && ctl->record_trace && k < ctl->trace_cap) trace[k].relres_true = rel;
     if (st == ST_RUNNING) {
       if (rel <= ctl->tol) {
         st = ASSG_CONVERGED;
@@ -415,18 +454,19 @@ __device__ void commit_loop(Ctl* ctl, assg_trace_t* trace, bool checked, double 
   ctl->status = st;
 }
 
-__global__ __launch_bounds__(256) void k_check(const Ctl* ctl, CsrView A,
+// One chunk per workgroup (a small grid: this kernel usually exits at once,
+// and an empty launch of one workgroup per row block costs ~15 us).
+__global__ __launch_bounds__(256) void k_check(const Ctl* ctls, CsrView A,
                                                const double* __restrict__ b,
                                                const double* __restrict__ x,
                                                double* __restrict__ part, int measure_only) {
   __shared__ double prod[SB_CAP];
   __shared__ double red[4];
+  int32_t b0, b1, sys;
+  const int32_t c = chunk_of(A, b0, b1, sys);
+  const Ctl* ctl = ctls + sys;
   if (!measure_only && (ctl->status != ST_RUNNING || !ctl->candidate)) return;
-  // a small grid looping over the row blocks: this kernel usually exits at
-  // once, and an empty launch of one workgroup per block costs ~15 us
   double my = 0.0;
-  int32_t b0, b1;
-  block_range(A.nblk, b0, b1);
   for (int32_t bb = b0; bb < b1; ++bb) {
     const BlockRows br(A, bb);
     double bi = 0.0;
@@ -441,19 +481,22 @@ __global__ __launch_bounds__(256) void k_check(const Ctl* ctl, CsrView A,
     __syncthreads();
   }
   my = block_sum<256>(my, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = my;
+  if (threadIdx.x == 0) part[c] = my;
 }
 
-// End of an outer loop (or HSCG iteration): the true relative residual when
-// a candidate was flagged, then the commit.
-__global__ __launch_bounds__(1024) void k_fin_check(Ctl* ctl, assg_trace_t* trace,
-                                                    const double* __restrict__ part, int n,
+// End of an outer loop (or HSCG iteration) of system blockIdx.x: the true
+// relative residual when a candidate was flagged, then the commit.
+__global__ __launch_bounds__(1024) void k_fin_check(Ctl* ctls, assg_trace_t* trace, CsrView A,
+                                                    const double* __restrict__ part,
                                                     int measure_only) {
   __shared__ double sh[16];
+  const int i = blockIdx.x;
+  Ctl* ctl = ctls + i;
   if (!measure_only && ctl->status != ST_RUNNING) return;
   const bool checked = measure_only || ctl->candidate;
+  const int32_t c0 = A.sys_chunk[i], c1 = A.sys_chunk[i + 1];
   double t = 0.0;
-  if (checked) t = finish_sum<1024>(part, n, sh);
+  if (checked) t = finish_sum<1024>(part + c0, c1 - c0, sh);
   if (threadIdx.x == 0) {
     const double rel = checked ? sqrt(t) / ctl->nb : -1.0;
     if (measure_only)
@@ -465,9 +508,9 @@ __global__ __launch_bounds__(1024) void k_fin_check(Ctl* ctl, assg_trace_t* trac
 
 void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A,
                   const double* b, const double* x, double* part, int measure_only) {
-  const int g = block_grid(A, 2048);
-  hipLaunchKernelGGL(k_check, dim3(g), dim3(256), 0, s, ctl, A, b, x, part, measure_only);
-  hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(1024), 0, s, ctl, trace, part, g, measure_only);
+  hipLaunchKernelGGL(k_check, dim3(A.nchunk), dim3(256), 0, s, ctl, A, b, x, part, measure_only);
+  hipLaunchKernelGGL(k_fin_check, dim3(A.nsys), dim3(1024), 0, s, ctl, A.nsys == 1 ? trace : nullptr,
+                     A, part, measure_only);
 }
 
 // ------------------------------------------------------------------ HSCG

@@ -16,20 +16,38 @@ namespace assg {
 constexpr int SB_ROWS = 256;
 constexpr int SB_CAP = 2048;
 
+// A matrix with its row-block partition.  A batch of independent systems
+// is one block-diagonal matrix (systems' rows and columns concatenated);
+// row blocks never straddle systems, and neither do the "chunks" (runs of
+// consecutive row blocks) that the reduction kernels give one workgroup
+// each.  A single solve is a batch of one: bsys and csys are null.
 struct CsrView {
   int64_t n, nnz;
   const int32_t* rp;
   const int32_t* ci;
   const double* va;
-  const int32_t* blk;   // nblk + 1 row starts of the row blocks
-  const int32_t* blke;  // nblk + 1 nonzero starts (row_ptr[blk[b]])
+  const int32_t* blk;        // nblk + 1 row starts of the row blocks
+  const int32_t* blke;       // nblk + 1 nonzero starts (row_ptr[blk[b]])
   int32_t nblk;
+  const int32_t* bsys;       // nblk: system of each row block (null: system 0)
+  const int32_t* cblk;       // nchunk + 1: first row block of each chunk
+  const int32_t* csys;       // nchunk: system of each chunk (null: system 0)
+  const int32_t* sys_chunk;  // nsys + 1: first chunk of each system
+  int32_t nchunk;            // a multiple of 8 (trailing chunks may be empty)
+  int32_t nsys;
 };
 
 // Greedy row-block partition (host): rows are appended while a block has
-// fewer than SB_ROWS rows and at most SB_CAP nonzeros.
-void make_blocks(const int32_t* row_ptr, int64_t n, std::vector<int32_t>& blk);
+// fewer than ``rows`` rows and at most ``cap`` (<= SB_CAP) nonzeros.
+void make_blocks(const int32_t* row_ptr, int64_t n, std::vector<int32_t>& blk,
+                 int rows = SB_ROWS, int cap = SB_CAP);
 
+// Chunks over the row blocks of each system (sys_blk: nsys + 1 block
+// starts): about ``target`` chunks in all, in proportion to each system's
+// blocks, at least one per system, padded with empty chunks to a multiple
+// of 8.
+void make_chunks(const std::vector<int32_t>& sys_blk, int target, std::vector<int32_t>& cblk,
+                 std::vector<int32_t>& csys, std::vector<int32_t>& sys_chunk);
 
 void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
 
@@ -37,7 +55,10 @@ void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
 // (two sums for the HSCG start).
 size_t reduce_doubles(int32_t nblk);
 
-// r = b - A x, pairs[0] = (r, r), ctl->nb = ||b||.
+// Kernels of the s-step path take the control blocks of all systems
+// (ctl[i] for system i) and run every system of the batch.
+
+// r = b - A x, pairs[0] = (r, r), ctl[i].nb = ||b_i||.
 void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, const double* x,
                   double2* pairs, double* part);
 
@@ -47,11 +68,14 @@ void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, do
 
 // Last sweep (P chain, level sbar) fused with the Gram partial sums.
 int last_gram_blocks(int sigma, int cus);
-void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A, int nblocks,
+// One workgroup per chunk; partials[pair * nchunk + chunk].
+void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A,
                       const double2* pairs, double* plast, int64_t ld, double* partials);
-void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, int nparts, const double* partials);
+void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, const CsrView& A,
+                        const double* partials);
 
-void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma);
+// One workgroup per system; the trace is recorded for a batch of one only.
+void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma, int nsys);
 
 void launch_recover(hipStream_t s, const Ctl* ctl, const CsrView& A, double2* pairs,
                     const double* plast, int64_t ld, double* x);
