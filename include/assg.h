@@ -239,6 +239,43 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
 assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t cap,
                              int64_t* count);
 
+/* ---------------------------------------------------------------- batches */
+
+#define ASSG_MAX_BATCH 2048   /* systems per batch */
+
+/* Prepares a batch of nsys independent systems (A: host array of nsys CSR
+ * descriptors of device matrices, each as for assg_analyze, 1 <= nsys <=
+ * ASSG_MAX_BATCH, total rows and nonzeros < 2^31).  The handle keeps one
+ * block-diagonal copy of the patterns (the systems' rows and columns
+ * concatenated; values are copied again at every solve), cuts row blocks
+ * that never straddle systems, and picks the row-block shape of the
+ * CSR-stream kernels by timing a product with each candidate (at most
+ * 256/128/64 rows and 2048/1024/512 nonzeros per block): see
+ * assg_batch_tuning.  Replaces any previous batch of the handle; the single
+ * solve's analysis is kept. */
+assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t* A);
+
+/* Algorithm 5 on every system of the analyzed batch at once.  Each kernel
+ * launch covers all systems; every system keeps its own control block
+ * (s-bar, s~, s_k, coefficients, Ritz estimates, c, basis parameters,
+ * stopping) and its blocks are skipped once it has stopped.  The outer loops
+ * run from a captured HIP graph (4 loops per replay), so the host enqueues
+ * one graph launch per 4 loops and reads the systems' states in between.
+ * A, nsys: as given to assg_batch_analyze (same row_ptr pointers, values may
+ * differ).  b, x: host arrays of nsys device pointers (n_i doubles each); x[i]
+ * holds x0 on entry and the solution on return.  opts apply to every system
+ * (record_trace must be 0, time_kernels is ignored).  info: host array of
+ * nsys results; solve_ms is the time of the whole batch. */
+assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* A,
+                               const double* const* b, double* const* x, const assg_opts_t* opts,
+                               assg_info_t* info);
+
+/* The row-block shape chosen by the last assg_batch_analyze (rows and
+ * nonzeros per block, host) and the measured product time of each candidate
+ * shape in microseconds (host array of 3: 256/2048, 128/1024, 64/512). */
+assg_status_t assg_batch_tuning(assg_handle_t h, int32_t* rows, int32_t* nnz_cap,
+                                double* candidate_us);
+
 /* ------------------------------------------------------- differentiation */
 
 /* out[k] = alpha * u[row(k)] * v[col(k)] for every stored nonzero k of A:

@@ -119,6 +119,11 @@ def lib():
         "assg_get_trace": (I32, [P, C.POINTER(AssgTrace), I64, C.POINTER(C.c_int64)]),
         "assg_spmv": (I32, [P, C.POINTER(AssgCsr), P, P]),
         "assg_csr_outer_on_pattern": (I32, [P, C.POINTER(AssgCsr), P, P, D, P]),
+        "assg_batch_analyze": (I32, [P, I32, C.POINTER(AssgCsr)]),
+        "assg_batch_solve": (I32, [P, I32, C.POINTER(AssgCsr), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), C.POINTER(AssgOpts),
+                                   C.POINTER(AssgInfo)]),
+        "assg_batch_tuning": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]),
         "assg_basis_gram": (I32, [P, C.POINTER(AssgCsr), P, P, I32, C.POINTER(D), C.POINTER(D),
                                   C.POINTER(D), P, C.POINTER(D)]),
         "assg_block_controller": (I32, [P, C.POINTER(D), I32, D, D, I32, I32,
@@ -297,6 +302,37 @@ def assg_get_trace(h: Handle) -> list:
 def assg_spmv(h: Handle, A: DeviceCSR, x, y):
     d = A.c()
     _check(lib().assg_spmv(h.ptr, C.byref(d), _dptr(x), _dptr(y)), h.ptr)
+
+
+def assg_batch_analyze(h: Handle, As: list):
+    """Prepares a batch of systems (DeviceCSR each) for assg_batch_solve."""
+    arr = (AssgCsr * len(As))(*[A.c() for A in As])
+    _check(lib().assg_batch_analyze(h.ptr, len(As), arr), h.ptr)
+
+
+def assg_batch_solve(h: Handle, As: list, bs: list, xs: list, opts: AssgOpts | None = None) -> list:
+    """Algorithm 5 on every system of the analyzed batch; xs[i] (CUDA float64)
+    holds x0_i on entry and the solution on return.  One info dict per system."""
+    n = len(As)
+    if not (len(bs) == len(xs) == n):
+        raise ValueError("As, bs and xs must have the same length")
+    opts = opts or assg_default_opts()
+    arr = (AssgCsr * n)(*[A.c() for A in As])
+    bp = (C.c_void_p * n)(*[_dptr(b).value for b in bs])
+    xp = (C.c_void_p * n)(*[_dptr(x).value for x in xs])
+    infos = (AssgInfo * n)()
+    _check(lib().assg_batch_solve(h.ptr, n, arr, bp, xp, C.byref(opts), infos), h.ptr)
+    return [_info_dict(i) for i in infos]
+
+
+def assg_batch_tuning(h: Handle) -> dict:
+    """Row-block shape picked by the batch autotuner and each candidate's
+    measured product time (us)."""
+    rows, cap = C.c_int32(), C.c_int32()
+    us = (C.c_double * 3)()
+    _check(lib().assg_batch_tuning(h.ptr, C.byref(rows), C.byref(cap), us), h.ptr)
+    return {"rows": rows.value, "nnz_cap": cap.value,
+            "candidates_us": {"256x2048": us[0], "128x1024": us[1], "64x512": us[2]}}
 
 
 def assg_csr_outer_on_pattern(h: Handle, A: DeviceCSR, u, v, alpha: float, out):

@@ -498,7 +498,8 @@ __global__ __launch_bounds__(1024) void k_fin_check(Ctl* ctls, assg_trace_t* tra
   double t = 0.0;
   if (checked) t = finish_sum<1024>(part + c0, c1 - c0, sh);
   if (threadIdx.x == 0) {
-    const double rel = checked ? sqrt(t) / ctl->nb : -1.0;
+    // b = 0 (x = 0, nothing iterated): the residual is exactly 0
+    const double rel = !checked ? -1.0 : (ctl->nb > 0.0 ? sqrt(t) / ctl->nb : (t == 0.0 ? 0.0 : INFINITY));
     if (measure_only)
       ctl->relres_true = rel;
     else
@@ -720,6 +721,19 @@ void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, cons
                           double alpha, double* out) {
   hipLaunchKernelGGL(k_outer_pattern, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, A, u, v,
                      alpha, out);
+}
+
+// dst[i] = src[i] + add (column indices of a system placed in a batch).
+__global__ void k_offset_copy(const int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                              int64_t n, int32_t add) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i] + add;
+}
+
+void launch_offset_copy(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n, int32_t add) {
+  const int64_t g = (n + 255) / 256;
+  if (g > 0)
+    hipLaunchKernelGGL(k_offset_copy, dim3((unsigned)g), dim3(256), 0, s, src, dst, n, add);
 }
 
 __global__ void k_pair_init(int64_t n, const double* __restrict__ p, const double* __restrict__ r,

@@ -101,6 +101,9 @@ void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, doubl
 void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
                           double alpha, double* out);
 
+// dst[i] = src[i] + add, i < n (batch assembly).
+void launch_offset_copy(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n, int32_t add);
+
 // Helpers of assg_basis_gram.
 void launch_pair_init(hipStream_t s, int64_t n, const double* p, const double* r, double2* pairs);
 void launch_export_Y(hipStream_t s, int64_t n, int sbar, const double2* pairs,

@@ -286,3 +286,19 @@ def symmetric_direction(A: sp.csr_matrix, seed: int) -> np.ndarray:
     d_k = z_k + z_t(k), z ~ N(0, 1)."""
     z = _rng(seed).standard_normal(A.nnz)
     return z + z[transpose_index(A)]
+
+
+def make_batch(count: int = 64, lo: int = 32, hi: int = 512, seed: int = 104) -> list:
+    """The batched workload: ``count`` unscaled 2D 5-point Poisson systems
+    A_i + c_i I with sides n_i ~ U{lo..hi}, shifts c_i ~ U(0, 0.1) lambda_max(A_i)
+    and right-hand sides b_i ~ N(0, 1) (seed + 1000 + i), x0 = 0."""
+    sides, shifts = batch_poisson2d_specs(count, lo, hi, seed)
+    out = []
+    for i, (m, c) in enumerate(zip(sides, shifts)):
+        A = (poisson2d(int(m), scaled=False) + c * sp.identity(int(m) * int(m), format="csr")).tocsr()
+        A.sort_indices()
+        A = sp.csr_matrix((A.data, A.indices.astype(np.int32), A.indptr.astype(np.int32)),
+                          shape=A.shape)
+        b = rhs_normal(A.shape[0], seed + 1000 + i)
+        out.append(Problem(name=f"batch{i}_poisson2d_{int(m)}", A=A, b=b, x0=np.zeros(A.shape[0])))
+    return out

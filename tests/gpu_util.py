@@ -2,6 +2,8 @@
 import math
 
 import numpy as np
+
+import oracle as O
 import pytest
 
 
@@ -51,3 +53,28 @@ def block_state_from_oracle(L, st):
         S.gamma[l] = ga[l] if l < ga.size else 1.0
         S.mu[l] = mu[l] if l < mu.size else 0.0
     return S
+
+
+def oracle_outer_spread(pr, seeds=12, **kw):
+    """Range of the oracle's outer-loop count when every basis entry it builds
+    carries one extra relative rounding error (normal noise of size 2^-53,
+    fixed seeds).  The GPU sums in another order than the host BLAS, so on a
+    problem whose s-selection sits near a threshold this is the spread any
+    correct implementation can land in."""
+    import oracle.sstep as S
+    base = S.sstep_basis
+    outs = []
+    try:
+        for seed in range(seeds):
+            rng = np.random.default_rng(seed)
+
+            def noisy(*a, _rng=rng, **k):
+                Y = base(*a, **k)
+                return Y * (1.0 + 2.0 ** -53 * _rng.standard_normal(Y.shape))
+
+            S.sstep_basis = noisy
+            _, info = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+            outs.append(info["outer"])
+    finally:
+        S.sstep_basis = base
+    return min(outs), max(outs)

@@ -6,7 +6,7 @@ import scipy.sparse as sp
 
 import oracle as O
 import spd_problems as P
-from gpu_util import torch_cuda
+from gpu_util import oracle_outer_spread, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -36,31 +36,6 @@ def _problem(name):
     raise KeyError(name)
 
 
-def _oracle_outer_spread(pr, seeds=12, **kw):
-    """Range of the oracle's outer-loop count when every basis entry it builds
-    carries one extra relative rounding error (normal noise of size 2^-53,
-    fixed seeds).  The GPU sums in another order than the host BLAS, so on a
-    problem whose s-selection sits near a threshold this is the spread any
-    correct implementation can land in."""
-    import oracle.sstep as S
-    base = S.sstep_basis
-    outs = []
-    try:
-        for seed in range(seeds):
-            rng = np.random.default_rng(seed)
-
-            def noisy(*a, _rng=rng, **k):
-                Y = base(*a, **k)
-                return Y * (1.0 + 2.0 ** -53 * _rng.standard_normal(Y.shape))
-
-            S.sstep_basis = noisy
-            _, info = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
-            outs.append(info["outer"])
-    finally:
-        S.sstep_basis = base
-    return min(outs), max(outs)
-
-
 def _solve_gpu(torch, L, h, pr, **opts):
     Ad = L.csr_to_device(pr.A)
     L.assg_analyze(h, Ad)
@@ -88,7 +63,7 @@ def test_solve_matches_oracle(env, name, basis, sigma):
     assert abs(ig["relres_true"] - rel_true) <= 1e-3 * rel_true
     if abs(ig["outer_iters"] - io["outer"]) > 1:
         # a trajectory that rounding alone moves: accept the oracle's own spread
-        lo, hi = _oracle_outer_spread(pr, s_max=sigma, tol=tol, basis=basis)
+        lo, hi = oracle_outer_spread(pr, s_max=sigma, tol=tol, basis=basis)
         assert lo - 1 <= ig["outer_iters"] <= hi + 1, (ig["outer_iters"], io["outer"], lo, hi)
     err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
     assert err <= 1e-8, err
