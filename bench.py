@@ -28,6 +28,30 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0        # MI355X HBM3E, vendor figure
 
 
+COUNTER_FILE = os.path.join(ROOT, "profiles", "hbm_counters_poisson3d_256.txt")
+KERNEL_SOURCES = ["kernels.hip", "device.hpp", "gram_plan.hpp", "launch.hpp", "ctl.hpp"]
+
+
+def measured_traffic():
+    """HBM bytes per k_sweep launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter summary of the 256^3 workload, or None when
+    the kernel sources no longer hash to the ones that were measured."""
+    import hashlib
+    try:
+        text = open(COUNTER_FILE).read()
+    except OSError:
+        return None
+    csrc = os.path.join(ROOT, "paper_1908_04081_amd", "csrc")
+    digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                     for f in KERNEL_SOURCES)).hexdigest()[:16]
+    if f"ctl.hpp): {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic k_sweep per launch (bytes):"):
+            return int(line.split(":")[1])
+    return None
+
+
 def mpk_bytes(n: int, nnz: int, s: int, chebyshev: bool):
     """Algorithmic HBM bytes of one outer loop's matrix powers + Gram (s
     levels), and of one two-chain sweep at level >= 2.
@@ -53,6 +77,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-compare", action="store_true", help="skip Newton and HSCG runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiable workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -159,6 +185,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if not args.no_batch:
+        extra["batched"] = bench_batch(L, P, torch)
+    if not args.no_grad:
+        extra["differentiable"] = bench_grad(L, P, torch)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pr, sigma, tol, last["outer_iters"])
@@ -189,7 +220,7 @@ def main():
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic() if args.size == 256 else None,
             "bytes_per_launch": sweep_b,
             "avg_launch_ms": round(sweep_avg_ms, 5),
             "launches": sweep_n,
@@ -209,6 +240,111 @@ def main():
     out.update(extra)
     print(json.dumps(out))
     L.assg_destroy(h)
+
+
+def bench_batch(L, P, torch):
+    """64 shifted 2D Poisson systems (sides 32..512): one batched solve
+    (every kernel launch covers all systems, outer loops replayed from a
+    captured graph) against the same systems solved one after another with
+    the single solve and with HSCG on the same GPU."""
+    probs = P.make_batch()
+    As = [L.csr_to_device(pr.A) for pr in probs]
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    h = L.assg_create()
+    t0 = time.perf_counter()
+    L.assg_batch_analyze(h, As)
+    t_an = time.perf_counter() - t0
+    opts = L.assg_default_opts(s_max=10, tol=1e-10, basis="chebyshev")
+
+    def batch():
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        inf = L.assg_batch_solve(h, As, bs, xs, opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, inf
+
+    batch()
+    t_batch, infos = min((batch() for _ in range(3)), key=lambda r: r[0])
+    worst = max(float(np.linalg.norm(pr.b - pr.A @ x.cpu().numpy()) / np.linalg.norm(pr.b))
+                for pr, x in zip(probs, xs))
+    hs = L.assg_create()
+
+    def sequential(hscg):
+        tot = 0.0
+        for A, b, x in zip(As, bs, xs):
+            L.assg_analyze(hs, A)
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if hscg:
+                L.assg_hscg_solve(hs, A, b, x, 1e-10, 0)
+            else:
+                L.assg_solve(hs, A, b, x, opts)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t
+        return tot
+
+    sequential(False)
+    t_seq = sequential(False)
+    t_hscg = sequential(True)
+    tune = L.assg_batch_tuning(h)
+    L.assg_destroy(h)
+    L.assg_destroy(hs)
+    out = {
+        "systems": len(probs), "rows": int(sum(pr.n for pr in probs)),
+        "nnz": int(sum(pr.A.nnz for pr in probs)),
+        "batch_solve_s": round(t_batch, 4),
+        "sequential_sstep_s": round(t_seq, 4), "sequential_hscg_s": round(t_hscg, 4),
+        "speedup_vs_sequential_sstep": round(t_seq / t_batch, 2),
+        "speedup_vs_sequential_hscg": round(t_hscg / t_batch, 2),
+        "all_converged": all(i["outcome"] == L.CONVERGED for i in infos),
+        "max_outer": max(i["outer_iters"] for i in infos),
+        "worst_relres_host": worst, "analyze_s": round(t_an, 3), "tuning": tune,
+    }
+    print(f"[bench] batch of {len(probs)}: {t_batch*1e3:.1f} ms (sequential s-step "
+          f"{t_seq*1e3:.1f} ms, HSCG {t_hscg*1e3:.1f} ms)", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_grad(L, P, torch):
+    """Differentiable workload: varcoef7 128^3, L = ||x - t||^2, gradients in b
+    and in A's values from the forward and adjoint solves at tol 1e-12."""
+    from paper_1908_04081_amd import autograd as AG
+    pr = P.make_config("varcoef7_128")
+    n = pr.n
+    pat = L.csr_to_device(pr.A)
+    h = L.assg_create()
+    L.assg_analyze(h, pat)
+    t = torch.from_numpy(P.rhs_normal(n, 2105)).cuda()
+    b0 = torch.from_numpy(pr.b).cuda()
+
+    def run():
+        val = pat.val.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = AG.solve(pat, val, b, handle=h, tol=1e-12, s_max=10, basis="chebyshev")
+        loss = ((x - t) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1
+
+    run()
+    fwd, bwd = run()
+    fi, ai = AG.last_info["forward"], AG.last_info["adjoint"]
+    L.assg_destroy(h)
+    print(f"[bench] differentiable: forward {fwd*1e3:.1f} ms, backward {bwd*1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    return {"workload": "varcoef7_128 (N=2,097,152), tol 1e-12", "forward_s": round(fwd, 4),
+            "backward_s": round(bwd, 4), "forward_outer": fi["outer_iters"],
+            "forward_outcome": fi["outcome_name"], "forward_relres": fi["relres_true"],
+            "adjoint_outer": ai["outer_iters"], "adjoint_outcome": ai["outcome_name"],
+            "adjoint_relres": ai["relres_true"]}
 
 
 def cpu_baseline(pr, sigma, tol, gpu_outer):

@@ -39,6 +39,12 @@ struct assg_handle_s {
   int32_t nchunk = 0;
   double* d_part = nullptr;      // per-workgroup partial sums (sized at analyze)
   int gram_blocks[MAXS + 1] = {0};
+  // captured graphs of the single solve's outer loops and of HSCG iterations,
+  // valid while the pointers and sizes they were captured with are unchanged
+  struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+  } g_sstep, g_hscg;
   // batch analysis (assg_batch_analyze) and its solve state
   struct Batch {
     int32_t nsys = 0;
@@ -290,6 +296,31 @@ void batch_blocks(const std::vector<std::vector<int32_t>>& rps, const std::vecto
   blke.push_back((int32_t)nnztot);
 }
 
+// The graph of ``enqueue``'s launches on the handle's stream for ``key``:
+// captured and instantiated when the key differs from the cached one.
+template <class F>
+assg_status_t cached_graph(assg_handle_t h, assg_handle_s::GraphCache& gc,
+                           const std::vector<const void*>& key, F enqueue) {
+  if (gc.exec && gc.key == key) return ASSG_OK;
+  if (gc.exec) HIP_OR_FAIL(h, hipGraphExecDestroy(gc.exec));
+  gc.exec = nullptr;
+  gc.key.clear();
+  hipGraph_t g = nullptr;
+  HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+  enqueue();
+  const hipError_t ce = hipStreamEndCapture(h->stream, &g);
+  if (ce != hipSuccess)
+    return fail(h, ASSG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  const hipError_t ie = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    gc.exec = nullptr;
+    return fail(h, ASSG_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
+  }
+  gc.key = key;
+  return ASSG_OK;
+}
+
 void batch_release(assg_handle_t h) {
   auto& B = h->bat;
   if (B.graph) (void)hipGraphExecDestroy(B.graph);
@@ -412,6 +443,8 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_blke) (void)hipFree(h->d_blke);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_part) (void)hipFree(h->d_part);
+  if (h->g_sstep.exec) (void)hipGraphExecDestroy(h->g_sstep.exec);
+  if (h->g_hscg.exec) (void)hipGraphExecDestroy(h->g_hscg.exec);
   batch_release(h);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -587,10 +620,38 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   double t_sweep = 0, t_sweep1 = 0, t_last = 0;
   int64_t n_sweep = 0, n_sweep1 = 0, n_last = 0;
 
+  int32_t status = ST_RUNNING;
+  if (!timing) {
+    // outer loops replayed from a captured graph of LOOPS_PER_GRAPH loops
+    constexpr int LOOPS_PER_GRAPH = 4;
+    const std::vector<const void*> key{A->row_ptr, A->col_idx, A->val, b, x, base, h->d_trace,
+                                       h->d_blk, h->d_chunks, h->d_part,
+                                       reinterpret_cast<const void*>((intptr_t)sigma),
+                                       reinterpret_cast<const void*>((intptr_t)n)};
+    st = cached_graph(h, h->g_sstep, key, [&]() {
+      for (int r = 0; r < LOOPS_PER_GRAPH; ++r) {
+        for (int l = 1; l < sigma; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
+        launch_last_gram(h->stream, h->d_ctl, sigma, Av, pairs, plast, lay.ld, grampart);
+        launch_gram_reduce(h->stream, h->d_ctl, sigma, Av, grampart);
+        launch_controller(h->stream, h->d_ctl, h->d_trace, sigma, 1);
+        launch_recover(h->stream, h->d_ctl, Av, pairs, plast, lay.ld, x);
+        launch_check(h->stream, h->d_ctl, h->d_trace, Av, b, x, h->d_part, 0);
+      }
+    });
+    if (st != ASSG_OK) return st;
+    while (true) {
+      HIP_OR_FAIL(h, hipGraphLaunch(h->g_sstep.exec, h->stream));
+      HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, h->stream));
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      status = h->h_status[0];
+      if (status != ST_RUNNING) break;
+    }
+  }
+  // with kernel timing: eager launches, events around each matrix-powers launch
   int64_t enqueued = 0;
   int batch = 1;
-  int32_t status = ST_RUNNING;
-  while (true) {
+  while (timing) {
     timed.clear();
     evn = 0;
     for (int bi = 0; bi < batch; ++bi, ++enqueued) {
@@ -707,22 +768,28 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   launch_h_init(h->stream, h->d_ctl, Av, b, x, r, p, h->d_part);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
-  int batch = 4;
-  int32_t status = ST_RUNNING;
-  while (true) {
-    for (int bi = 0; bi < batch; ++bi) {
+  // iterations replayed from a captured graph of ITERS_PER_GRAPH iterations
+  constexpr int ITERS_PER_GRAPH = 16;
+  const std::vector<const void*> key{A->row_ptr, A->col_idx, A->val, b, x, base, h->d_blk,
+                                     h->d_chunks, h->d_part,
+                                     reinterpret_cast<const void*>((intptr_t)n)};
+  st = cached_graph(h, h->g_hscg, key, [&]() {
+    for (int it = 0; it < ITERS_PER_GRAPH; ++it) {
       launch_h_spmv(h->stream, h->d_ctl, Av, p, w, h->d_part);
       launch_h_update(h->stream, h->d_ctl, Av, x, r, p, w, h->d_part);
       launch_h_dir(h->stream, h->d_ctl, Av, r, p);
       launch_check(h->stream, h->d_ctl, nullptr, Av, b, x, h->d_part, 0);
     }
-    HIP_OR_FAIL(h, hipGetLastError());
+  });
+  if (st != ASSG_OK) return st;
+  int32_t status = ST_RUNNING;
+  while (true) {
+    HIP_OR_FAIL(h, hipGraphLaunch(h->g_hscg.exec, h->stream));
     HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_ctl, sizeof(int32_t), hipMemcpyDeviceToHost,
                                   h->stream));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     status = h->h_status[0];
     if (status != ST_RUNNING) break;
-    if (batch < 32) batch *= 2;
   }
   HIP_OR_FAIL(h, hipEventRecord(h->ev_stop, h->stream));
   if (status != ASSG_CONVERGED) {

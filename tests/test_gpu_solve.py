@@ -154,3 +154,29 @@ def test_deterministic(env):
     x1, i1 = _solve_gpu(torch, L, h, pr)
     x2, i2 = _solve_gpu(torch, L, h, pr)
     assert np.array_equal(x1, x2) and i1["outer_iters"] == i2["outer_iters"]
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion27_14"])
+def test_graph_replay_matches_eager_launches(env, name):
+    """The outer loops replayed from the captured graph (default) and launched
+    one by one (kernel timing on) run the same kernels in the same order:
+    bit-identical iterates and counts, over two solves in a row (the second
+    replays the cached graph) and for HSCG as well."""
+    torch, L, h = env
+    pr = _problem(name)
+    runs = []
+    for timing in (0, 1, 0):
+        xg, ig = _solve_gpu(torch, L, h, pr, s_max=10, tol=1e-10, time_kernels=timing)
+        runs.append((xg, ig))
+    for xg, ig in runs[1:]:
+        assert np.array_equal(xg, runs[0][0])
+        assert ig["outer_iters"] == runs[0][1]["outer_iters"]
+    Ad = L.csr_to_device(pr.A)
+    L.assg_analyze(h, Ad)
+    b = torch.from_numpy(pr.b).cuda()
+    xs = []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
+        xs.append(x.cpu().numpy())
+    assert np.array_equal(xs[0], xs[1])
