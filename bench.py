@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip Newton and HSCG runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiable workload")
+    ap.add_argument("--no-diffusion", action="store_true",
+                    help="skip the 160^3 27-point diffusion workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -185,6 +187,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if not args.no_diffusion:
+        extra["diffusion27_160"] = bench_diffusion(L, P, torch)
     if not args.no_batch:
         extra["batched"] = bench_batch(L, P, torch)
     if not args.no_grad:
@@ -240,6 +244,40 @@ def main():
     out.update(extra)
     print(json.dumps(out))
     L.assg_destroy(h)
+
+
+def bench_diffusion(L, P, torch):
+    """27-point lognormal (sigma = 2) diffusion on 160^3, Jacobi-scaled, b ~
+    N(0, 1), sigma = 10, tol 1e-10: both bases and HSCG, best of two each."""
+    pr = P.make_config("diffusion27_160")
+    A = L.csr_to_device(pr.A)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    h = L.assg_create()
+    L.assg_analyze(h, A)
+    out = {"n": pr.n, "nnz": int(pr.A.nnz)}
+    for basis in ("chebyshev", "newton", "hscg"):
+        best, inf = 1e9, None
+        for _ in range(2):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if basis == "hscg":
+                inf = L.assg_hscg_solve(h, A, b, x, 1e-10, 0)
+            else:
+                inf = L.assg_solve(h, A, b, x, L.assg_default_opts(s_max=10, tol=1e-10,
+                                                                   basis=basis))
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        out[basis] = {"s": round(best, 4), "outer_iters": inf["outer_iters"],
+                      "total_iters": inf["total_iters"], "outcome": inf["outcome_name"],
+                      "relres_true": inf["relres_true"]}
+    out["speedup_vs_hscg"] = round(out["hscg"]["s"] / out["chebyshev"]["s"], 3)
+    L.assg_destroy(h)
+    print(f"[bench] diffusion27_160: chebyshev {out['chebyshev']['s']*1e3:.1f} ms, newton "
+          f"{out['newton']['s']*1e3:.1f} ms, hscg {out['hscg']['s']*1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def bench_batch(L, P, torch):
