@@ -26,6 +26,21 @@ places where the paper is silent or inconsistent follow these readings
 * basis parameters switch from monomial once m > 1 and are regenerated after
   every outer loop from the latest estimates, unless lambda_max - lambda_min
   is not positive and finite (then the previous ones are kept).
+
+Comparison variants of Section 5 (``variant``):
+
+* "improved": Algorithm 5 as above, c = xi~ of (4.6);
+* "improved_c_ratio": Algorithm 5 with c = lambda~max / lambda~min, updated
+  with the estimates every iteration (Section 5.1; c_1 until the first
+  update);
+* "improved_c_one": Algorithm 5 with the constant c = 1 (Section 5.1);
+* "old": the adaptive s-step CG of Algorithm 2 with the monomial basis
+  throughout and a constant c_k = ``c_const`` (the algorithm leaves c_k to
+  the user; 1 by default): s~ by (3.2), gamma = kappa(Y_{k,s~}) of the
+  selected basis, break after step j when gamma >= eps* / (c_k eps rho_{j+1})
+  with the current relative residual rho_{j+1};
+* "fixed": fixed s-step CG, monomial basis, s_k = s-bar = sigma in every
+  outer loop (no selection, no break); the stopping test is the same.
 """
 from __future__ import annotations
 
@@ -50,9 +65,12 @@ def _kappa_sub(G, idx) -> float:
     return math.sqrt(hi / lo)
 
 
+VARIANTS = ("improved", "improved_c_ratio", "improved_c_one", "old", "fixed")
+
+
 def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-10,
                       basis="chebyshev", max_outer=None, max_iters=None, record=True,
-                      record_gram=False):
+                      record_gram=False, variant="improved", c_const=1.0):
     """Solve A x = b by the improved adaptive s-step CG (Algorithm 5).
 
     Parameters follow the algorithm's inputs: sigma = ``s_max``,
@@ -63,6 +81,11 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
     With ``record_gram`` each record also keeps G (paper order) and the
     carried state at the start of the loop (for step-by-step comparisons).
     """
+    if variant not in VARIANTS:
+        raise ValueError(f"unknown variant {variant!r}")
+    improved = variant.startswith("improved")
+    if not improved:
+        basis = "monomial"
     A = A.tocsr() if hasattr(A, "tocsr") else A
     b = np.asarray(b, dtype=np.float64)
     N = b.size
@@ -87,7 +110,7 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
     r = b - A @ x
     p = r.copy()
     psi = 1.0
-    c = u ** -0.5
+    c = {"improved_c_one": 1.0, "old": float(c_const)}.get(variant, u ** -0.5)
     m = 0
     params = make_params("monomial", sigma)
     mt_max = mt_min = None
@@ -126,6 +149,8 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
                 stilde = l
             else:
                 break
+        if variant == "fixed":
+            stilde = sbar
         gam = {l: kappa[l + 1] for l in range(1, stilde)}
         idx = sub_indices(sbar, stilde)
         Gs = G[np.ix_(idx, idx)]
@@ -170,7 +195,10 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
                 eta = math.sqrt(beta_prev / alpha_prev)
                 lmax = mt_max.step(eta, zeta)
                 lmin = mt_min.step(eta, zeta)
-                c = max(1.0, lmax * math.sqrt(psi / lmin))
+                if variant == "improved":
+                    c = max(1.0, lmax * math.sqrt(psi / lmin))          # (4.6)
+                elif variant == "improved_c_ratio":
+                    c = lmax / lmin
             alpha_prev, beta_prev = alpha, beta
             info["alphas"].append(alpha)
             info["betas"].append(beta)
@@ -180,8 +208,12 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
             if rho <= tol:
                 candidate = True
                 break
-            if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):
-                break
+            if improved:
+                if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):   # (4.7)
+                    break
+            elif variant == "old":
+                if j < stilde - 1 and kappa[stilde] >= tol / (c * u * rho):
+                    break
         rec.update(sk=sk, phi=phi, c=c, lmin=lmin, lmax=lmax, psi=psi,
                    relres_updated=math.sqrt(rGr) / nb, candidate=candidate)
         if record_gram:
@@ -197,7 +229,7 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
         p = Ys @ pc
         m += sk
         s_prev = sk
-        if m > 1 and np.isfinite(lmax) and np.isfinite(lmin) and lmax - lmin > 0.0:
+        if improved and m > 1 and np.isfinite(lmax) and np.isfinite(lmin) and lmax - lmin > 0.0:
             params = make_params(basis, sigma, lmin, lmax) if basis != "monomial" \
                 else make_params("monomial", sigma)
         k += 1
