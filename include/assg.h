@@ -73,6 +73,18 @@ typedef enum {
   ASSG_BASIS_CHEBYSHEV = 2
 } assg_basis_t;
 
+/* Method run by assg_solve / assg_batch_solve: Algorithm 5 (default) or one
+ * of the comparison methods of Section 5.  The monomial-basis methods
+ * ignore opts.basis. */
+typedef enum {
+  ASSG_IMPROVED = 0,          /* Algorithm 5, c = xi~ of (4.6)                          */
+  ASSG_IMPROVED_C_RATIO = 1,  /* Algorithm 5 with c = lambda~max / lambda~min (5.1)     */
+  ASSG_IMPROVED_C_ONE = 2,    /* Algorithm 5 with c = 1 (Section 5.1)                   */
+  ASSG_OLD_ADAPTIVE = 3,      /* Algorithm 2, monomial basis, constant c = opts.c_const: s~ by
+                                 (3.2), break when kappa(Y_{k,s~}) >= eps* / (c eps rho_{j+1}) */
+  ASSG_FIXED_SSTEP = 4        /* fixed s-step CG, monomial basis, s_k = sigma, no break   */
+} assg_variant_t;
+
 /* Sparse SPD matrix, CSR, all arrays device pointers (caller-owned). */
 typedef struct {
   int64_t n;               /* rows = columns, >= 1                               */
@@ -93,13 +105,17 @@ typedef struct {
   int64_t max_iters;   /* cap on total inner iterations; 0 -> 10 n               */
   int32_t record_trace;/* 1: keep one assg_trace_t per outer loop (assg_get_trace) */
   int32_t time_kernels;/* 1: time the matrix-powers kernels with HIP events       */
+  int32_t variant;     /* assg_variant_t (default ASSG_IMPROVED)                  */
+  int32_t pad0;
+  double c_const;      /* c of ASSG_OLD_ADAPTIVE, > 0 (default 1)                 */
 } assg_opts_t;
 
 /* Result of a solve (host struct filled by the library). */
 typedef struct {
   int32_t outcome;          /* assg_outcome_t                                     */
   int32_t pad0;
-  int64_t outer_iters;      /* outer loops k (= global synchronizations)          */
+  int64_t outer_iters;      /* outer loops completed (= global synchronizations;  */
+                            /* a loop ending in breakdown/divergence not counted) */
   int64_t total_iters;      /* inner iterations m                                 */
   double relres_updated;    /* (r'^T G r')^{1/2} / ||b|| at the end               */
   double relres_true;       /* ||b - A x|| / ||b|| of the returned x              */

@@ -25,6 +25,7 @@ CONVERGED, STAGNATED, DIVERGED, BREAKDOWN, MAX_ITER, RUNNING = 0, 1, 2, 3, 4, 5
 OUTCOME_NAMES = {0: "CONVERGED", 1: "STAGNATED", 2: "DIVERGED", 3: "BREAKDOWN", 4: "MAX_ITER",
                  5: "RUNNING"}
 BASIS = {"monomial": 0, "newton": 1, "chebyshev": 2}
+VARIANT = {"improved": 0, "improved_c_ratio": 1, "improved_c_one": 2, "old": 3, "fixed": 4}
 
 
 class AssgCsr(C.Structure):
@@ -36,7 +37,8 @@ class AssgOpts(C.Structure):
     _fields_ = [("s_max", C.c_int32), ("s_init", C.c_int32), ("growth", C.c_int32),
                 ("basis", C.c_int32), ("tol", C.c_double), ("max_outer", C.c_int64),
                 ("max_iters", C.c_int64), ("record_trace", C.c_int32),
-                ("time_kernels", C.c_int32)]
+                ("time_kernels", C.c_int32), ("variant", C.c_int32), ("pad0", C.c_int32),
+                ("c_const", C.c_double)]
 
 
 class AssgInfo(C.Structure):
@@ -176,6 +178,8 @@ def assg_default_opts(**overrides) -> AssgOpts:
     for k, v in overrides.items():
         if k == "basis" and isinstance(v, str):
             v = BASIS[v]
+        if k == "variant" and isinstance(v, str):
+            v = VARIANT[v]
         setattr(o, k, v)
     return o
 

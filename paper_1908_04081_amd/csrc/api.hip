@@ -229,6 +229,25 @@ bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_sta
 
 // Workgroups of the persistent last-sweep + Gram kernel: the occupancy
 // limit over all CUs, but no more than row blocks (rounded up to 8).
+// Outer loops completed: a loop that ended in breakdown or divergence is
+// committed on the device (its trace record is kept) but not counted.
+int64_t completed_loops(const Ctl* c) {
+  const bool broke = c->status == ASSG_BREAKDOWN || c->status == ASSG_DIVERGED;
+  return (broke && c->k > 0) ? c->k - 1 : c->k;
+}
+
+// The method of opts in a fresh control block: the monomial-basis methods
+// keep theta = 0, gamma = 1, mu = 0 throughout; the starting c is 1 for
+// Algorithm 5 with c = 1 and c_const for the old adaptive method.
+void apply_variant(Ctl* c, const assg_opts_t* o) {
+  c->variant = o->variant;
+  c->c_const = o->c_const;
+  if (o->variant == ASSG_OLD_ADAPTIVE || o->variant == ASSG_FIXED_SSTEP)
+    c->basis = ASSG_BASIS_MONOMIAL;
+  if (o->variant == ASSG_IMPROVED_C_ONE) c->c = 1.0;
+  if (o->variant == ASSG_OLD_ADAPTIVE) c->c = o->c_const;
+}
+
 // The kernels' view of the analyzed single matrix (a batch of one).
 CsrView view(assg_handle_t h, const assg_csr_t* A) {
   CsrView v{};
@@ -358,6 +377,8 @@ assg_status_t assg_default_opts(assg_opts_t* o) {
   o->max_iters = 0;
   o->record_trace = 0;
   o->time_kernels = 0;
+  o->variant = ASSG_IMPROVED;
+  o->c_const = 1.0;
   return ASSG_OK;
 }
 
@@ -554,6 +575,10 @@ static assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o) {
   if (!(o->tol > 0.0 && o->tol < 1.0)) return fail(h, ASSG_ERR_INVALID_ARG, "tol must be in (0,1)");
   if (o->max_outer < 0 || o->max_iters < 0)
     return fail(h, ASSG_ERR_INVALID_ARG, "iteration caps must be >= 0");
+  if (o->variant < ASSG_IMPROVED || o->variant > ASSG_FIXED_SSTEP)
+    return fail(h, ASSG_ERR_INVALID_ARG, "unknown variant");
+  if (o->variant == ASSG_OLD_ADAPTIVE && !(o->c_const > 0.0 && std::isfinite(o->c_const)))
+    return fail(h, ASSG_ERR_INVALID_ARG, "c_const must be positive and finite");
   return ASSG_OK;
 }
 
@@ -603,6 +628,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   c->max_outer = max_outer;
   c->max_iters = max_iters;
   c->tol = opts->tol;
+  apply_variant(c, opts);
 
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
@@ -705,7 +731,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   float ms = 0.f;
   HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
   info->outcome = c->status;
-  info->outer_iters = c->k;
+  info->outer_iters = completed_loops(c);
   info->total_iters = c->m;
   info->relres_updated = c->relres_upd;
   info->relres_true = c->relres_true;
@@ -1171,6 +1197,7 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
     c->max_outer = opts->max_outer > 0 ? opts->max_outer : max_iters;
     c->max_iters = max_iters;
     c->tol = opts->tol;
+    apply_variant(c, opts);
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(B.dctl, B.hctl, (size_t)nsys * sizeof(Ctl),
                                 hipMemcpyHostToDevice, h->stream));
@@ -1233,7 +1260,7 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
     assg_info_t& o = info[i];
     std::memset(&o, 0, sizeof(o));
     o.outcome = c->status;
-    o.outer_iters = c->k;
+    o.outer_iters = completed_loops(c);
     o.total_iters = c->m;
     o.relres_updated = c->relres_upd;
     o.relres_true = c->relres_true;

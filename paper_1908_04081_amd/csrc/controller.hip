@@ -240,6 +240,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   const double rGr0 = fmax(sG[1 * MAXC + 1], 0.0);
   const double rho_m = sqrt(rGr0) / nb;
   const double thr = (rho_m > 0.0) ? tol / (c * u * rho_m) : INFINITY;
+  const int variant = ctl->variant;
   int st = 1;
   for (int l = 1; l <= sbar; ++l) {
     if (sKappa[l] <= thr)
@@ -247,6 +248,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
     else
       break;
   }
+  if (variant == ASSG_FIXED_SSTEP) st = sbar;   // fixed s-step CG: the whole basis
   const int n = 2 * st + 1;
 
   // ---- inner loop (interleaved coordinates; lane i owns coordinate i and
@@ -315,7 +317,10 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       }
       lmax = mx_omega;
       lmin = 1.0 / mn_omega;
-      c = fmax(1.0, lmax * sqrt(psi / lmin));               // (4.6)
+      if (variant == ASSG_IMPROVED)
+        c = fmax(1.0, lmax * sqrt(psi / lmin));             // (4.6)
+      else if (variant == ASSG_IMPROVED_C_RATIO)
+        c = lmax / lmin;                                    // Section 5.1
     }
     alpha_prev = alpha;
     beta_prev = beta;
@@ -325,7 +330,12 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
     }
     if (!isfinite(alpha) || !isfinite(beta)) { outcome = ASSG_DIVERGED; break; }
     if (rho <= tol) { candidate = 1; break; }
-    if (j < st - 1 && sKappa[j + 2] >= tol / (c * u * phi)) break;   // (4.7), gamma_{j+1}
+    if (variant <= ASSG_IMPROVED_C_ONE) {
+      if (j < st - 1 && sKappa[j + 2] >= tol / (c * u * phi)) break;   // (4.7), gamma_{j+1}
+    } else if (variant == ASSG_OLD_ADAPTIVE) {
+      // Algorithm 2: gamma = kappa(Y_{k,s~}) against the current residual
+      if (j < st - 1 && sKappa[st] >= tol / (c * u * rho)) break;
+    }
   }
 
   // ---- results

@@ -33,12 +33,14 @@ struct alignas(256) Ctl {
   int32_t fail_streak;   // failed true-residual confirmations
   int32_t flags;
   int32_t mode;          // 0: s-step, 1: HSCG
+  int32_t variant;       // assg_variant_t
   int64_t m;             // inner iterations done
 
   // -------------------------------------------------------------- options
   int32_t sigma, growth, basis, record_trace;
   int64_t trace_cap, max_outer, max_iters;
   double tol;
+  double c_const;        // c of the old adaptive method
 
   // -------------------------------------------------------------- scalars
   double nb;             // ||b||

@@ -1,0 +1,100 @@
+"""The comparison methods of Section 5 on the GPU (the same kernels, the
+controller switching its s-selection, c and break rules) against the
+oracle's variants."""
+import numpy as np
+import pytest
+
+import oracle as O
+import spd_problems as P
+from gpu_util import oracle_outer_spread, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+OUTCOME = {O.Outcome.CONVERGED: 0, O.Outcome.STAGNATED: 1, O.Outcome.DIVERGED: 2,
+           O.Outcome.BREAKDOWN: 3, O.Outcome.MAX_ITER: 4}
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = torch_cuda()
+    import paper_1908_04081_amd as L
+    L.lib()
+    h = L.assg_create()
+    yield torch, L, h
+    L.assg_destroy(h)
+
+
+def _problem(name):
+    if name == "poisson2d_45":
+        return P.make_config("poisson2d_64", size=45)
+    if name == "poisson2d_64":
+        return P.make_config("poisson2d_64")
+    return P.make_config("varcoef7_128", size=10)
+
+
+def _gpu(torch, L, h, pr, **opts):
+    Ad = L.csr_to_device(pr.A)
+    L.assg_analyze(h, Ad)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    info = L.assg_solve(h, Ad, b, x, L.assg_default_opts(**opts))
+    return x.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("name", ["poisson2d_45", "varcoef7_10"])
+@pytest.mark.parametrize("variant", ["improved_c_ratio", "improved_c_one", "old", "fixed"])
+@pytest.mark.parametrize("sigma", [5, 10])
+def test_variant_matches_oracle(env, name, variant, sigma):
+    torch, L, h = env
+    pr = _problem(name)
+    kw = dict(s_max=sigma, tol=1e-10, basis="chebyshev", variant=variant, max_outer=3000)
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    xg, ig = _gpu(torch, L, h, pr, s_init=sigma, growth=sigma, **kw)
+    assert ig["outcome"] == OUTCOME[io["outcome"]], (ig["outcome_name"], io["outcome"])
+    if io["outcome"] != O.Outcome.CONVERGED:
+        return
+    rel = np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b)
+    assert rel <= 1e-10
+    if abs(ig["outer_iters"] - io["outer"]) > 1:
+        lo, hi = oracle_outer_spread(pr, **kw)
+        assert lo - 1 <= ig["outer_iters"] <= hi + 1, (ig["outer_iters"], io["outer"], lo, hi)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_fixed_sstep_breaks_down_at_s15(env):
+    """sigma = 15 on the 64 x 64 Poisson workload: the monomial basis of
+    fixed s-step CG is numerically singular in the first loop, on both sides."""
+    torch, L, h = env
+    pr = _problem("poisson2d_64")
+    kw = dict(s_max=15, tol=1e-10, variant="fixed", max_outer=3000)
+    _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    _, ig = _gpu(torch, L, h, pr, s_init=15, growth=15, **kw)
+    assert io["outcome"] == O.Outcome.BREAKDOWN
+    assert ig["outcome"] == L.BREAKDOWN and ig["outer_iters"] == io["outer"]
+
+
+def test_old_adaptive_degrades_at_s15(env):
+    """The same workload with Algorithm 2 (monomial basis, c = 1): a regime
+    where rounding steers the run (the oracle needs 9x HSCG's iterations),
+    so only the behaviour is compared: neither side converges in about
+    HSCG's iteration count, while Algorithm 5 does on both."""
+    torch, L, h = env
+    pr = _problem("poisson2d_64")
+    _, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
+    kw = dict(s_max=15, tol=1e-10, variant="old", max_outer=3000)
+    _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    _, ig = _gpu(torch, L, h, pr, s_init=15, growth=15, **kw)
+    slow = lambda ok, iters: (not ok) or iters > 2 * ih["iters"]
+    assert slow(io["outcome"] == O.Outcome.CONVERGED, io["iters"])
+    assert slow(ig["outcome"] == L.CONVERGED, ig["total_iters"]), ig
+    _, ii = _gpu(torch, L, h, pr, s_max=15, s_init=15, growth=15, tol=1e-10)
+    assert ii["outcome"] == L.CONVERGED and ii["total_iters"] <= 1.05 * ih["iters"]
+
+
+def test_bad_variant_options_are_rejected(env):
+    torch, L, h = env
+    pr = _problem("poisson2d_45")
+    with pytest.raises(L.AssgError):
+        _gpu(torch, L, h, pr, variant=7)
+    with pytest.raises(L.AssgError):
+        _gpu(torch, L, h, pr, variant="old", c_const=0.0)

@@ -31,15 +31,21 @@ def test_fixed_runs_full_blocks():
     assert all(t["sk"] == 6 for t in tr[:-1])
 
 
-def test_old_with_negligible_c_is_fixed():
-    """c_k -> 0 makes (3.2) and the break test of Algorithm 2 always pass /
-    never fire: the run is fixed s-step CG, bit for bit."""
+def test_old_with_negligible_c_never_limits_s():
+    """c_k -> 0 puts the threshold of (3.2) and of Algorithm 2's break test
+    out of reach: s~ is the largest l whose leading blocks all have a
+    positive definite Gram matrix (kappa finite; the first loop has p = r,
+    so only l = 1... fails there), and every loop but the last runs all s~
+    steps."""
     pr = _pr()
-    xf, jf = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=8, tol=1e-10, variant="fixed")
-    xo, jo = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=8, tol=1e-10, variant="old",
-                                 c_const=1e-200)
-    assert np.array_equal(xf, xo)
-    assert [t["sk"] for t in jf["trace"]] == [t["sk"] for t in jo["trace"]]
+    _, jo = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=5, tol=1e-10, variant="old",
+                                c_const=1e-200)
+    assert jo["outcome"] == O.Outcome.CONVERGED
+    for t in jo["trace"]:
+        fin = np.isfinite(t["kappa"])
+        expect = max(1, int(np.argmin(fin)) if not fin.all() else len(fin))
+        assert t["stilde"] == expect, (t["k"], t["stilde"], t["kappa"])
+    assert all(t["sk"] == t["stilde"] for t in jo["trace"][:-1])
 
 
 def test_old_with_huge_c_takes_single_steps():
