@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip Newton and HSCG runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-system batched workload")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiable workload")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the table of the paper's comparison methods")
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the 160^3 27-point diffusion workload")
     ap.add_argument("--copy-calib", action="store_true",
@@ -189,6 +191,8 @@ def main():
 
     if not args.no_diffusion:
         extra["diffusion27_160"] = bench_diffusion(L, P, torch)
+    if not args.no_variants:
+        extra["variants"] = bench_variants(L, P, torch)
     if not args.no_batch:
         extra["batched"] = bench_batch(L, P, torch)
     if not args.no_grad:
@@ -244,6 +248,59 @@ def main():
     out.update(extra)
     print(json.dumps(out))
     L.assg_destroy(h)
+
+
+def bench_variants(L, P, torch):
+    """The layout of the paper's tables (Section 5) on synthetic matrices:
+    for eps* in {the relative residual HSCG attains, 1e-6} and s = sigma in
+    {5, 10, 15}, outer loops (total iterations) of fixed s-step CG, the old
+    adaptive method (monomial basis, c = 1), Algorithm 5 with the Newton and
+    the Chebyshev basis, and HSCG; "-" marks breakdown or divergence and
+    "- [r]" a run that stopped at relative residual r above eps*."""
+    mats = {"poisson2d_64 (N=4096, scaled)": P.make_config("poisson2d_64"),
+            "diffusion27_16 (N=4096, lognormal sigma=2, scaled)":
+                P.make_config("diffusion27_160", size=16)}
+    h = L.assg_create()
+    tables = {}
+    for label, pr in mats.items():
+        A = L.csr_to_device(pr.A)
+        L.assg_analyze(h, A)
+        b = torch.from_numpy(pr.b).cuda()
+        x = torch.zeros_like(b)
+        x.zero_()
+        hs = L.assg_hscg_solve(h, A, b, x, 1e-15, 20 * pr.n)
+        attain = float(f"{max(hs['relres_true'], 1e-15) * 1.1:.1e}")
+        rows = []
+        for tol in (attain, 1e-6):
+            x.zero_()
+            hc = L.assg_hscg_solve(h, A, b, x, tol, 20 * pr.n)
+            for sigma in (5, 10, 15):
+                cells = {}
+                for col, variant, basis in (("fixed", "fixed", "monomial"),
+                                            ("old adaptive", "old", "monomial"),
+                                            ("impr. Newton", "improved", "newton"),
+                                            ("impr. Chebyshev", "improved", "chebyshev")):
+                    x.zero_()
+                    i = L.assg_solve(h, A, b, x, L.assg_default_opts(
+                        s_max=sigma, s_init=sigma, growth=sigma, tol=tol, basis=basis,
+                        variant=variant, max_outer=5000, max_iters=20 * pr.n))
+                    if i["outcome"] == L.CONVERGED:
+                        cells[col] = f"{i['outer_iters']} ({i['total_iters']})"
+                    elif i["outcome"] in (L.BREAKDOWN, L.DIVERGED) or not \
+                            (i["relres_true"] < 1.0):
+                        cells[col] = "-"
+                    else:
+                        cells[col] = f"- [{i['relres_true']:.0e}]"
+                cells["HSCG"] = (str(hc["total_iters"]) if hc["outcome"] == L.CONVERGED
+                                 else f"- [{hc['relres_true']:.0e}]")
+                rows.append({"eps": tol, "s": sigma, **cells})
+        tables[label] = rows
+    L.assg_destroy(h)
+    for label, rows in tables.items():
+        print(f"[bench] {label}", file=sys.stderr)
+        for r in rows:
+            print("[bench]   " + "  ".join(f"{k}={v}" for k, v in r.items()), file=sys.stderr)
+    return tables
 
 
 def bench_diffusion(L, P, torch):
