@@ -38,7 +38,7 @@ struct assg_handle_s {
   int32_t* d_chunks = nullptr;   // chunk starts (nchunk + 1) then system chunk starts (2)
   int32_t nchunk = 0;
   double* d_part = nullptr;      // per-workgroup partial sums (sized at analyze)
-  int gram_blocks[MAXS + 1] = {0};
+  int gram_blocks[MAXS + 1] = {0};   // resident last-sweep workgroups per sigma (chunk count)
   // captured graphs of the single solve's outer loops and of HSCG iterations,
   // valid while the pointers and sizes they were captured with are unchanged
   struct GraphCache {
@@ -227,8 +227,6 @@ bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_sta
   return true;
 }
 
-// Workgroups of the persistent last-sweep + Gram kernel: the occupancy
-// limit over all CUs, but no more than row blocks (rounded up to 8).
 // Outer loops completed: a loop that ended in breakdown or divergence is
 // committed on the device (its trace record is kept) but not counted.
 int64_t completed_loops(const Ctl* c) {

@@ -168,7 +168,7 @@ __device__ __forceinline__ double gmv(const double* grow, double v) {
   return s;
 }
 
-constexpr int CTL_WAVES = 8;   // wave w estimates blocks w+1, w+9 (256 VGPRs per lane)
+constexpr int CTL_WAVES = 8;   // waves estimating the leading blocks (largest first)
 
 __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__ ctls,
                                                      assg_trace_t* __restrict__ trace) {
