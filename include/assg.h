@@ -232,12 +232,18 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
 
 /* ------------------------------------------------------------- the solves */
 
-/* Algorithm 5: improved adaptive s-step CG.  b (device, n) is read; x
- * (device, n) holds x0 on entry and the solution on return.  ``workspace``
- * (device, >= assg_workspace_size bytes) may be NULL, in which case the
- * handle allocates and keeps one.  info (host) receives the outcome and
- * iteration counts.  The relative residual is ||b - A x|| / ||b||; with
- * b = 0 the result is x = 0, CONVERGED. */
+/* Algorithm 5: improved adaptive s-step CG (or a comparison method, see
+ * opts.variant).  b (device, n) is read; x (device, n) holds x0 on entry and
+ * the solution on return.  ``workspace`` (device, >= assg_workspace_size
+ * bytes) may be NULL, in which case the handle allocates and keeps one.
+ * info (host) receives the outcome and iteration counts.  The relative
+ * residual is ||b - A x|| / ||b||; with b = 0 the result is x = 0,
+ * CONVERGED.  Every decision is taken on the device: the kernels of 4 outer
+ * loops are captured once into a HIP graph (kept on the handle while the
+ * pointers, sizes and s_max stay the same) and replayed, the host reading
+ * the status word between replays; loops replayed after the end exit at
+ * once.  With opts.time_kernels = 1 the same kernels are launched one by one
+ * instead, with HIP events around the matrix-powers launches. */
 assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
                          const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
                          assg_info_t* info);
