@@ -180,3 +180,24 @@ def test_graph_replay_matches_eager_launches(env, name):
         L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
         xs.append(x.cpu().numpy())
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("name", ["poisson2d_45", "diffusion27_14"])
+@pytest.mark.parametrize("basis", ["chebyshev", "newton"])
+def test_growing_sbar_matches_oracle(env, name, basis):
+    """s-bar_0 = 2 and f = 1: the basis grows by one level per loop up to
+    sigma = 10, so sweeps past the loop's s-bar exit and the fused last sweep
+    runs with fewer columns than its compiled width."""
+    torch, L, h = env
+    pr = _problem(name)
+    kw = dict(s_max=10, s_init=2, growth=1, tol=1e-10, basis=basis)
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    xg, ig = _solve_gpu(torch, L, h, pr, record_trace=1, **kw)
+    assert ig["outcome"] == L.CONVERGED and io["outcome"] == O.Outcome.CONVERGED
+    tr = L.assg_get_trace(h)
+    assert [t["sbar"] for t in tr[:5]] == [t["sbar"] for t in io["trace"][:5]]
+    if abs(ig["outer_iters"] - io["outer"]) > 1:
+        lo, hi = oracle_outer_spread(pr, **kw)
+        assert lo - 1 <= ig["outer_iters"] <= hi + 1
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+    assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
