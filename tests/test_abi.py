@@ -1,0 +1,69 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/assg.h declares, agrees with the Python mirrors of its structs, and
+its host-only entry points (defaults, basis parameters of (2.7)/(2.8),
+workspace sizes, status strings) work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "assg.h")
+
+
+def _lib():
+    import paper_1908_04081_amd as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1908_04081_amd import build
+        build.build()
+    return L, L.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:assg_status_t|const char\*|int32_t)\s+(assg_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for must in ("assg_solve", "assg_hscg_solve", "assg_analyze", "assg_batch_solve",
+                 "assg_csr_outer_on_pattern", "assg_basis_gram", "assg_block_controller"):
+        assert must in names
+    assert len(names) >= 20
+
+
+def test_library_exports_every_declared_function():
+    _, lib = _lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_the_python_mirrors():
+    L, lib = _lib()
+    sizes = (C.c_int64 * 6)()
+    assert lib.assg_struct_sizes(sizes, 6) == 6
+    mirrors = [L.AssgOpts, L.AssgInfo, L.AssgTrace, L.AssgBlockState, L.AssgBlockResult,
+               L.AssgCsr]
+    assert [C.sizeof(m) for m in mirrors] == list(sizes)
+
+
+def test_host_only_entry_points():
+    L, lib = _lib()
+    o = L.assg_default_opts()
+    assert (o.s_max, o.s_init, o.growth, o.basis, o.tol, o.variant, o.c_const) == \
+        (10, 10, 10, 2, 1e-10, 0, 1.0)
+    assert lib.assg_status_string(0) == b"ok"
+    assert L.assg_workspace_size(1000, 10) > 21 * 1000 * 8
+    # Chebyshev (2.8) as read here: theta = centre, gamma_0 = d/2, gamma_l = mu_l = d/4
+    th, ga, mu = L.assg_basis_params("chebyshev", 0.5, 2.5, 4)
+    assert np.allclose(th, 1.5) and ga[0] == 1.0 and np.allclose(ga[1:], 0.5)
+    assert np.allclose(mu, 0.5)
+    # Newton (2.7): theta_0 = lmax, theta_1 = lmin, Leja order inside
+    th, ga, mu = L.assg_basis_params("newton", 1.0, 3.0, 3)
+    assert th[0] == 3.0 and th[1] == 1.0 and abs(th[2] - 2.0) < 1e-15
+    assert np.all(ga == 1.0) and np.all(mu == 0.0)
+    with pytest.raises(L.AssgError):
+        L.assg_basis_params("newton", 2.0, 1.0, 3)

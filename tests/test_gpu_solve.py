@@ -201,3 +201,21 @@ def test_growing_sbar_matches_oracle(env, name, basis):
         assert lo - 1 <= ig["outer_iters"] <= hi + 1
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
     assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
+
+
+def test_cfg1_trace_matches_golden(env):
+    """The 64 x 64 Poisson workload against the stored oracle trace
+    (tests/golden/poisson2d_64_chebyshev_s10.txt): the same s-bar, s~ and
+    s_k in every outer loop and the same updated residuals to 1e-8."""
+    import os
+    torch, L, h = env
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "poisson2d_64_chebyshev_s10.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    pr = _problem("poisson2d_64")
+    _, ig = _solve_gpu(torch, L, h, pr, s_max=10, tol=1e-10, basis="chebyshev", record_trace=1)
+    tr = L.assg_get_trace(h)
+    assert len(tr) == len(rows)
+    for t, r in zip(tr, rows):
+        assert (t["k"], t["sbar"], t["stilde"], t["sk"]) == tuple(int(v) for v in r[:4])
+        assert abs(t["relres_updated"] - float(r[4])) <= 1e-8 * float(r[4])
