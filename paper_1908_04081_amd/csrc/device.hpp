@@ -13,8 +13,21 @@ constexpr int WAVE = 64;
 constexpr int NXCD = 8;          // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 // ---------------------------------------------------------------- loads
+// Streaming (non-temporal) accesses for data read or written once per
+// kernel: they do not displace the gathered vectors from the caches, and on
+// this part they raise the bandwidth of many concurrent streams.
 template <typename T>
 __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldnt2(const double2* p) {
+  const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stnt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stnt2(double2* p, double2 v) {
+  const dvec2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<dvec2*>(p));
+}
 
 // ------------------------------------------------------- wave reductions
 __device__ __forceinline__ double wave_sum(double v) {

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int
     double2 xo = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
     if (br.own) {
       xo = X[br.row];
-      if (mu != 0.0) x2 = X2[br.row];
+      if (mu != 0.0) x2 = ldnt2(X2 + br.row);
     }
     double ax, ay;
     stream_rows<2, 256, SB_CAP>(A.ci, A.va, Src2{X}, br.e0, br.ne, br.rs, br.re, br.own, prod,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int
         yx -= mu * x2.x;
         yy -= mu * x2.y;
       }
-      Yo[br.row] = make_double2(yx / ga, yy / ga);
+      stnt2(Yo + br.row, make_double2(yx / ga, yy / ga));
     }
     __syncthreads();
   }
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
       const double2* src = (row < nr) ? pairs + (size_t)l * ld + r0 + row : g_zero_rows + lane;
       __builtin_amdgcn_global_load_lds(
           (const void*)src,
-          (void __attribute__((address_space(3)))*)(tile + l * TS + ((i & 3) << 6)), 16, 0, 0);
+          (void __attribute__((address_space(3)))*)(tile + l * TS + ((i & 3) << 6)), 16, 0, 2);   // nt: streamed once
     }
     double a, unused;
     if (br.ne <= SB_CAP) {
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
         y = a - th * tile[(s - 1) * TS + tid].x;
         if (mu != 0.0) y -= mu * tile[(s - 2) * TS + tid].x;
         y = y / ga;
-        plast[br.row] = y;
+        stnt(plast + br.row, y);
       }
       tile[s * TS + tid] = make_double2(y, 0.0);
     }
@@ -398,11 +398,11 @@ __global__ __launch_bounds__(256) void k_recover(const Ctl* __restrict__ ctls, C
   const double* __restrict__ plevel =
       (sk == sbar) ? plast : reinterpret_cast<const double*>(pairs + (size_t)sk * ld);
   const int pstride = (sk == sbar) ? 1 : 2;
-  const double yl = plevel[pstride * row];
-  const double x0 = x[row];
+  const double yl = ldnt(plevel + pstride * row);
+  const double x0 = ldnt(x + row);
   double xs = 0.0, ps = 0.0, rs = 0.0;
   for (int l = 0; l < sk; ++l) {
-    const double2 y = pairs[(size_t)l * ld + row];
+    const double2 y = ldnt2(pairs + (size_t)l * ld + row);
     xs = fma(ctl->cx[2 * l], y.x, xs);
     xs = fma(ctl->cx[2 * l + 1], y.y, xs);
     ps = fma(ctl->cp[2 * l], y.x, ps);
@@ -413,8 +413,8 @@ __global__ __launch_bounds__(256) void k_recover(const Ctl* __restrict__ ctls, C
   xs = fma(ctl->cx[2 * sk], yl, xs);
   ps = fma(ctl->cp[2 * sk], yl, ps);
   rs = fma(ctl->cr[2 * sk], yl, rs);
-  x[row] = x0 + xs;
-  pairs[row] = make_double2(ps, rs);
+  stnt(x + row, x0 + xs);
+  stnt2(pairs + row, make_double2(ps, rs));
 }
 
 void launch_recover(hipStream_t s, const Ctl* ctl, const CsrView& A, double2* pairs,
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_h_spmv(const Ctl* ctl, CsrView A,
     stream_rows<1, 256, SB_CAP>(A.ci, A.va, Src1{p}, br.e0, br.ne, br.rs, br.re, br.own, prod,
                                 red, v, unused);
     if (br.own) {
-      w[br.row] = v;
+      stnt(w + br.row, v);
       my = pi * v;
     }
   }
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(256) void k_h_dir(const Ctl* ctl, CsrView A,
   const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
   if ((int)threadIdx.x >= nr) return;
   const int64_t row = (int64_t)r0 + threadIdx.x;
-  p[row] = r[row] + ctl->h_beta * p[row];
+  stnt(p + row, ldnt(r + row) + ctl->h_beta * ldnt(p + row));
 }
 
 void launch_h_dir(hipStream_t s, const Ctl* ctl, const CsrView& A, const double* r, double* p) {
@@ -646,10 +646,10 @@ __global__ __launch_bounds__(256) void k_h_update(const Ctl* ctl, CsrView A,
     const int32_t r0 = A.blk[bb], nr = A.blk[bb + 1] - r0;
     if ((int)threadIdx.x < nr) {
       const int64_t row = (int64_t)r0 + threadIdx.x;
-      const double pi = p[row], wi = w[row], xi = x[row], ri = r[row];
-      x[row] = xi + alpha * pi;
+      const double pi = ldnt(p + row), wi = ldnt(w + row), xi = ldnt(x + row), ri = ldnt(r + row);
+      stnt(x + row, xi + alpha * pi);
       const double rn = ri - alpha * wi;
-      r[row] = rn;
+      stnt(r + row, rn);
       my = rn * rn;
     }
   }
