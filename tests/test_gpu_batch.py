@@ -87,10 +87,20 @@ def test_batch_zero_rhs_and_breakdown_are_per_system(env):
 
 
 def test_batch_repeat_is_deterministic(env):
+    """Two solves after one analysis are bitwise identical.  (A new analysis
+    may pick another row-block shape by timing, and with it another grouping
+    of the Gram partial sums, so only the same analysis fixes the rounding.)"""
     torch, L, h = env
     probs = _mixed_batch()
-    x1, i1 = _run(torch, L, h, probs, s_max=10, tol=1e-10)
-    x2, i2 = _run(torch, L, h, probs, s_max=10, tol=1e-10)
+    As = [L.csr_to_device(pr.A) for pr in probs]
+    L.assg_batch_analyze(h, As)
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    runs = []
+    for _ in range(2):
+        xs = [torch.from_numpy(pr.x0.copy()).cuda() for pr in probs]
+        infos = L.assg_batch_solve(h, As, bs, xs, L.assg_default_opts(s_max=10, tol=1e-10))
+        runs.append(([x.cpu().numpy() for x in xs], infos))
+    (x1, i1), (x2, i2) = runs
     for a, b_, p, q in zip(x1, x2, i1, i2):
         assert np.array_equal(a, b_)
         assert p["outer_iters"] == q["outer_iters"]
