@@ -29,7 +29,7 @@ PEAK_HBM_GBPS = 8000.0        # MI355X HBM3E, vendor figure
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "hbm_counters_poisson3d_256.txt")
-KERNEL_SOURCES = ["kernels.hip", "device.hpp", "gram_plan.hpp", "launch.hpp", "ctl.hpp"]
+KERNEL_SOURCES = ["kernels.hip", "device.hpp", "launch.hpp", "ctl.hpp"]
 
 
 def measured_traffic():

@@ -16,7 +16,6 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
-#include "gram_plan.hpp"
 #include "launch.hpp"
 
 namespace assg {
@@ -214,14 +213,20 @@ void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, do
 // Zero source of the direct-to-LDS basis loads for rows past a block.
 __device__ double2 g_zero_rows[64];
 
-// For each row block (<= 256 rows): the block's s-bar basis pairs go from
+// For each row block (<= 256 rows): the source gathers of the block's
+// CSR-stream products are issued first, then its s-bar basis pairs go from
 // HBM straight into a pair-major LDS tile (direct-to-LDS loads, no
-// registers), the CSR-stream products give P_sbar for the block's rows
-// (stored as the tile's level s-bar), then every wave adds its share of the
-// unique products Y_a * Y_b over the tile's rows to register accumulators.
-// The next block's nonzeros are fetched before the Gram products, so their
-// HBM latency overlaps them.  Rows past the block and columns past
-// 2 sbar + 1 are zero.
+// registers), and one wait covers both.  The products give P_sbar for the
+// block's rows (stored as the tile's level s-bar); then G = Y^T Y is
+// accumulated on the matrix cores: each wave takes 256/W of the block's
+// rows, four rows per v_mfma_f64_16x16x4_f64, for the 16 x 16 blocks
+// (I, J), I <= J, of the columns padded to NG * 16 (columns past 2 sbar + 1
+// and rows past the block are zero).  The next block's nonzeros and row
+// ranges are fetched before the Gram, and its bounds one block earlier
+// still.  At the end the waves' accumulators are added in wave order and
+// the unique entries written as this chunk's partials.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
 template <int NC, int W>
 __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctls, CsrView A,
                                                       const double2* __restrict__ pairs,
@@ -232,70 +237,200 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   const Ctl* ctl = ctls + sys;
   if (ctl->status != ST_RUNNING) return;
   constexpr int NT = 64 * W;
-  constexpr int QMAX = GramPlanHolder<NC, W>::QMAX;
   constexpr int TS = SB_ROWS;
-  constexpr int NL = (NC + 1) / 2;   // pair levels of the tile (the last one holds P_sbar, 0)
-  __shared__ double2 tile[NL * TS];
-  __shared__ double prod[SB_CAP];
+  constexpr int TP = TS + 1;                 // padded level stride (LDS banks)
+  constexpr int NL = (NC + 1) / 2;           // pair levels (the last holds P_sbar, 0)
+  constexpr int NG = (NC + 15) / 16;         // 16-column groups
+  constexpr int NB = NG * (NG + 1) / 2;      // accumulated 16 x 16 blocks
+  constexpr int TILE_D = 2 * NL * TP;        // tile doubles
+  constexpr int LDS_D = TILE_D + SB_CAP;
+  // the waves' accumulators are added WR waves at a time through the LDS
+  constexpr int WR = (W * NB * 256 <= LDS_D) ? W : (W / 2 * NB * 256 <= LDS_D) ? W / 2
+                     : (W / 4 * NB * 256 <= LDS_D) ? W / 4 : 1;
+  static_assert(WR * NB * 256 <= LDS_D, "accumulator staging exceeds the tile");
+  __shared__ double lds[LDS_D];
   __shared__ double red[W];
+  double2* const tile = reinterpret_cast<double2*>(lds);
+  double* const prod = lds + TILE_D;
+  const double* const tcol = lds;            // column c of row r: tcol[2 (c/2 TP + r) + c%2]
   const int s = ctl->sbar;
   const double th = ctl->theta[s - 1];
   const double ga = ctl->gamma[s - 1];
   const double mu = (s >= 2) ? ctl->mu[s - 2] : 0.0;
   const double* __restrict__ xsrc = reinterpret_cast<const double*>(pairs + (size_t)(s - 1) * ld);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = (s + 1) * TS + tid; i < NL * TS; i += NT) tile[i] = make_double2(0.0, 0.0);
-  double acc[QMAX];
+  for (int i = (s + 1) * TP + tid; i < NL * TP; i += NT) tile[i] = make_double2(0.0, 0.0);
+  mfma_d4 acc[NB];
 #pragma unroll
-  for (int q = 0; q < QMAX; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NB; ++q) acc[q] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  // this lane's column within each 16-column group, and its tile offsets
+  int coff[NG];
+  bool cin[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int c = 16 * g + (lane & 15);
+    cin[g] = c < 2 * NL;
+    coff[g] = cin[g] ? 2 * ((c >> 1) * TP) + (c & 1) : 0;
+  }
+  const int krow = lane >> 4;                // row within a group of four
+  constexpr int RPW = TS / W;                // rows per wave
 
-  RowFetch<NT, SB_CAP> f;
-  BlockRows br(A, b0 < b1 ? b0 : 0);
-  if (b0 < b1 && br.ne <= SB_CAP && br.ne > 0) f.issue(A.ci, A.va, br.e0, br.ne);
-  for (int32_t b = b0; b < b1; ++b) {
-    // basis pairs of the block's rows: 64-row chunks, one load per chunk and
-    // wave instruction; lanes past the block read zeros
-    const int32_t r0 = br.r0, nr = br.nr;
-    for (int i = wave; i < 4 * s; i += W) {
-      const int l = i >> 2, row = ((i & 3) << 6) + lane;
-      const double2* src = (row < nr) ? pairs + (size_t)l * ld + r0 + row : g_zero_rows + lane;
-      __builtin_amdgcn_global_load_lds(
-          (const void*)src,
-          (void __attribute__((address_space(3)))*)(tile + l * TS + ((i & 3) << 6)), 16, 0, 2);   // nt: streamed once
+  // Row-block bounds come through the scalar cache one block ahead (the
+  // partition is read-only), so a block's fetch never waits for them.
+  typedef const __attribute__((address_space(4))) int32_t kint;
+  kint* const kblk = (kint*)A.blk;
+  kint* const kblke = (kint*)A.blke;
+  struct Rows {
+    int32_t r0, nr, e0, ne, rs, re;
+  };
+  auto bounds = [&](int32_t b, Rows& r) {
+    r.r0 = kblk[b];
+    r.nr = kblk[b + 1] - r.r0;
+    r.e0 = kblke[b];
+    r.ne = kblke[b + 1] - r.e0;
+  };
+  auto own_range = [&](Rows& r) {   // vector loads, consumed after the next drain
+    r.rs = r.re = 0;
+    if (tid < r.nr) {
+      r.rs = A.rp[(int64_t)r.r0 + tid] - r.e0;
+      r.re = A.rp[(int64_t)r.r0 + tid + 1] - r.e0;
     }
-    double a, unused;
-    if (br.ne <= SB_CAP) {
-      fetched_rows<1, NT, SB_CAP>(f, SrcP{xsrc}, br.ne, br.rs, br.re, br.own, prod, a, unused,
-                                  true);
+  };
+  constexpr int SMAX = (NC - 1) / 2;   // basis levels in the tile (sbar <= SMAX)
+  constexpr int ND = 4 * SMAX;        // 64-row loads per block
+  constexpr int NDW = (ND + W - 1) / W;
+  constexpr int K = SB_CAP / NT;
+  const int rlo = wave * RPW;
+  RowFetch<NT, SB_CAP> f;
+  Rows cur{}, nxt{};
+  if (b0 < b1) {
+    bounds(b0, cur);
+    own_range(cur);
+    if (cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
+    if (b0 + 1 < b1) bounds(b0 + 1, nxt);
+  }
+  for (int32_t b = b0; b < b1; ++b) {
+    // the block's source gathers, then its basis pairs (64-row chunks, a
+    // fixed number per wave: levels past sbar and lanes past the block read
+    // zeros), then one wait for both
+    const bool fits = cur.ne <= SB_CAP;
+    double gx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gx[k] = 0.0;
+    if (fits && cur.ne > 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) gx[k] = xsrc[2 * (int64_t)f.c[k]];
+    }
+#pragma unroll
+    for (int j = 0; j < NDW; ++j) {
+      const int i = wave + j * W;
+      if (ND % W == 0 || i < ND) {
+        const int l = i >> 2, row = ((i & 3) << 6) + lane;
+        const double2* src =
+            (l < s && row < cur.nr) ? pairs + (size_t)l * ld + cur.r0 + row : g_zero_rows + lane;
+        __builtin_amdgcn_global_load_lds(
+            (const void*)src,
+            (void __attribute__((address_space(3)))*)(tile + l * TP + ((i & 3) << 6)), 16, 0,
+            2);   // nt: streamed once
+      }
+    }
+    const bool own = tid < cur.nr;
+    double a = 0.0, unused;
+    if (fits) {
+      // every wave waits for its loads before the barrier, so the tile is
+      // complete after it
+      __builtin_amdgcn_s_waitcnt(0);
+      if (cur.ne > 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int32_t e = tid + NT * k;
+          if (e < cur.ne) prod[e] = f.a[k] * gx[k];
+        }
+      }
+      __syncthreads();
+      if (own)
+        for (int32_t e = cur.rs; e < cur.re; ++e) a += prod[e];
     } else {
       __builtin_amdgcn_s_waitcnt(0);
-      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, br.e0, br.ne, red, a, unused);
+      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, cur.e0, cur.ne, red, a, unused);
     }
-    // tile complete (every wave waited for its loads before the barrier)
     if (tid < TS) {
       double y = 0.0;
-      if (br.own) {
-        y = a - th * tile[(s - 1) * TS + tid].x;
-        if (mu != 0.0) y -= mu * tile[(s - 2) * TS + tid].x;
+      if (own) {
+        y = a - th * tile[(s - 1) * TP + tid].x;
+        if (mu != 0.0) y -= mu * tile[(s - 2) * TP + tid].x;
         y = y / ga;
-        stnt(plast + br.row, y);
+        stnt(plast + (int64_t)cur.r0 + tid, y);
       }
-      tile[s * TS + tid] = make_double2(y, 0.0);
+      tile[s * TP + tid] = make_double2(y, 0.0);
     }
-    const int nsub = (nr + 63) >> 6;
     if (b + 1 < b1) {
-      br = BlockRows(A, b + 1);
-      if (br.ne <= SB_CAP && br.ne > 0) f.issue(A.ci, A.va, br.e0, br.ne);
+      cur = nxt;
+      own_range(cur);
+      if (cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
+      if (b + 2 < b1) bounds(b + 2, nxt);
     }
     __syncthreads();
-    for (int q = 0; q < nsub; ++q) gram_accum<NC, W, TS>(wave, acc, tile + q * 64, lane);
+    // Gram on the matrix cores: rows [wave RPW, (wave + 1) RPW), four at a
+    // time (rows past the block are zero in the tile)
+#pragma unroll
+    for (int k = 0; k < RPW / 4; ++k) {
+      double v[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) v[g] = cin[g] ? tcol[coff[g] + 2 * (rlo + 4 * k + krow)] : 0.0;
+      int q = 0;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int gj = gi; gj < NG; ++gj, ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[gi], v[gj], acc[q], 0, 0, 0);
+    }
     __syncthreads();
   }
-  gram_flush_all<NC, W>(wave, acc, lane, partials, A.nchunk, chunk);
+  // the waves' accumulators through the LDS, added in wave order, then the
+  // unique entries (a <= b, row-major upper triangle) as this chunk's partials
+  constexpr int NP = NC * (NC + 1) / 2;
+  constexpr int NPT = (NP + NT - 1) / NT;
+  int at[NPT];
+  double sum[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    sum[k] = 0.0;
+    at[k] = -1;
+    const int p = tid + k * NT;
+    if (p < NP) {
+      int ia = 0, qq = p;
+      while (qq >= NC - ia) {
+        qq -= NC - ia;
+        ++ia;
+      }
+      const int ib = ia + qq;
+      const int gi = ia >> 4, gj = ib >> 4, i = ia & 15, j = ib & 15;
+      const int q = gi * NG - (gi * (gi - 1)) / 2 + (gj - gi);
+      at[k] = (q * 4 + (i >> 2)) * 64 + j + 16 * (i & 3);   // D[i][j]: lane j + 16 (i % 4), reg i / 4
+    }
+  }
+  for (int w0 = 0; w0 < W; w0 += WR) {
+    if (wave >= w0 && wave < w0 + WR) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lds[(((wave - w0) * NB + q) * 4 + e) * 64 + lane] = acc[q][e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (at[k] >= 0)
+        for (int w = 0; w < WR; ++w) sum[k] += lds[w * NB * 256 + at[k]];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k)
+    if (at[k] >= 0) partials[(size_t)(tid + k * NT) * A.nchunk + chunk] = sum[k];
 }
 
 template <int NC>
-constexpr int gram_waves() { return NC <= 21 ? 4 : 8; }
+constexpr int gram_waves() { return 8; }
 
 template <int NC>
 static int last_gram_blocks_nc(int cus) {

