@@ -50,7 +50,7 @@ typedef enum {
   ASSG_ERR_HIP = -2,          /* a HIP call failed; assg_last_error() has the text   */
   ASSG_ERR_ALLOC = -3,        /* device or pinned allocation failed                  */
   ASSG_ERR_UNSUPPORTED = -4,  /* no usable gfx950 device                             */
-  ASSG_ERR_NOT_ANALYZED = -5  /* the matrix differs from the last assg_analyze call  */
+  ASSG_ERR_NOT_ANALYZED = -5  /* n, nnz, row_ptr or col_idx differ from the last analysis */
 } assg_status_t;
 
 /* Outcome of a solve (Section 5 reports converged, diverged "-" and
@@ -87,10 +87,10 @@ typedef enum {
 
 /* Sparse SPD matrix, CSR, all arrays device pointers (caller-owned). */
 typedef struct {
-  int64_t n;               /* rows = columns, >= 1                               */
-  int64_t nnz;             /* entries, < 2^31                                    */
+  int64_t n;               /* rows = columns, 1 <= n < 2^31                      */
+  int64_t nnz;             /* entries, 1 <= nnz < 2^31                           */
   const int32_t* row_ptr;  /* n + 1, row_ptr[0] = 0, row_ptr[n] = nnz            */
-  const int32_t* col_idx;  /* nnz, sorted within each row                         */
+  const int32_t* col_idx;  /* nnz, in [0, n), sorted within each row              */
   const double* val;       /* nnz                                                 */
 } assg_csr_t;
 
@@ -225,9 +225,13 @@ assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes);
 
 /* Prepares A for the kernels: reads row_ptr once (device -> host) and cuts
  * the rows into the row blocks of the CSR-stream kernels (at most 256 rows
- * and 2048 nonzeros each; a longer row is a block of its own).  Must be
- * called again when the sparsity pattern changes; values may change freely
- * between solves. */
+ * and 2048 nonzeros each; a longer row is a block of its own).  Checks
+ * row_ptr (starts at 0, ends at nnz, nondecreasing) on the host and every
+ * column index against [0, n) on the device; a failed check returns
+ * ASSG_ERR_INVALID_ARG and leaves the handle with no analysis (solves then
+ * return ASSG_ERR_NOT_ANALYZED).  Must be called again when the sparsity
+ * pattern changes (row_ptr and col_idx must not change between analysis
+ * and solve); values may change freely between solves. */
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
 
 /* ------------------------------------------------------------- the solves */
@@ -266,8 +270,9 @@ assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t ca
 #define ASSG_MAX_BATCH 2048   /* systems per batch */
 
 /* Prepares a batch of nsys independent systems (A: host array of nsys CSR
- * descriptors of device matrices, each as for assg_analyze, 1 <= nsys <=
- * ASSG_MAX_BATCH, total rows and nonzeros < 2^31).  The handle keeps one
+ * descriptors of device matrices, each as for assg_analyze and checked the
+ * same way, 1 <= nsys <= ASSG_MAX_BATCH, total rows and nonzeros < 2^31;
+ * after a failed check the handle holds no batch).  The handle keeps one
  * block-diagonal copy of the patterns (the systems' rows and columns
  * concatenated; values are copied again at every solve), cuts row blocks
  * that never straddle systems, and picks the row-block shape of the

@@ -77,13 +77,25 @@ assg_status_t fail(assg_handle_t h, assg_status_t st, const std::string& msg) {
 
 
 bool csr_ok(const assg_csr_t* A) {
-  return A && A->n >= 1 && A->nnz >= 1 && A->nnz < (int64_t(1) << 31) && A->row_ptr &&
-         A->col_idx && A->val;
+  return A && A->n >= 1 && A->n < (int64_t(1) << 31) && A->nnz >= 1 &&
+         A->nnz < (int64_t(1) << 31) && A->row_ptr && A->col_idx && A->val;
+}
+
+assg_status_t check_columns(assg_handle_t h, const int32_t* ci, int64_t nnz, int64_t n) {
+  HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
+  launch_check_cols(h->stream, ci, nnz, (int32_t)n, h->d_flag);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (h->h_status[0] != 0) return fail(h, ASSG_ERR_INVALID_ARG, "column index outside [0, n)");
+  return ASSG_OK;
 }
 
 assg_status_t check_analyzed(assg_handle_t h, const assg_csr_t* A) {
   if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
-  if (A->n != h->an_n || A->nnz != h->an_nnz || A->row_ptr != h->an_rp)
+  if (A->n != h->an_n || A->nnz != h->an_nnz || A->row_ptr != h->an_rp ||
+      A->col_idx != h->an_ci)
     return fail(h, ASSG_ERR_NOT_ANALYZED, "matrix not analyzed (call assg_analyze)");
   return ASSG_OK;
 }
@@ -317,6 +329,7 @@ assg_status_t assg_create(assg_handle_t* out, void* stream) {
   HIP_OR_FAIL(h, hipMalloc(&h->d_ctl, sizeof(Ctl)));
   HIP_OR_FAIL(h, hipHostMalloc(&h->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIP_OR_FAIL(h, hipHostMalloc(&h->h_status, 128, hipHostMallocDefault));
+  HIP_OR_FAIL(h, hipMalloc(&h->d_flag, sizeof(int32_t)));
   leja_table(h->leja, MAXS);
   for (int s = 1; s <= MAXS; ++s) h->gram_blocks[s] = last_gram_blocks(s, h->cus);
   *out = h;
@@ -337,6 +350,7 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->g_hscg.exec) (void)hipGraphExecDestroy(h->g_hscg.exec);
   batch_release(h);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
+  if (h->d_flag) (void)hipFree(h->d_flag);
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->h_status) (void)hipHostFree(h->h_status);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
@@ -355,6 +369,7 @@ assg_status_t assg_set_stream(assg_handle_t h, void* stream) {
 
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   if (!h) return ASSG_ERR_INVALID_ARG;
+  h->an_n = -1;   // no solve runs on an earlier analysis once a new one is asked for
   if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
   std::vector<int32_t> rp((size_t)A->n + 1);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
@@ -366,6 +381,10 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
     return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
   for (int64_t i = 0; i < A->n; ++i)
     if (rp[i + 1] < rp[i]) return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr must be nondecreasing");
+  {
+    const assg_status_t st = check_columns(h, A->col_idx, A->nnz, A->n);
+    if (st != ASSG_OK) return st;
+  }
   std::vector<int32_t> blk, blke;
   make_blocks(rp.data(), A->n, blk);
   blke.resize(blk.size());
@@ -400,6 +419,7 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   h->an_n = A->n;
   h->an_nnz = A->nnz;
   h->an_rp = A->row_ptr;
+  h->an_ci = A->col_idx;
   h->err.clear();
   return ASSG_OK;
 }

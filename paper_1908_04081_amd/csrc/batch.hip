@@ -117,6 +117,8 @@ assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t
       return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
     for (int64_t r = 0; r < A[i].n; ++r)
       if (rp[r + 1] < rp[r]) return fail(h, ASSG_ERR_INVALID_ARG, "row_ptr must be nondecreasing");
+    const assg_status_t st = check_columns(h, A[i].col_idx, A[i].nnz, A[i].n);
+    if (st != ASSG_OK) return st;
   }
   B.nsys = nsys;
   B.ntot = row0[nsys];

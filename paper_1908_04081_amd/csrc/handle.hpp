@@ -21,6 +21,7 @@ struct assg_handle_s {
   assg::Ctl* d_ctl = nullptr;
   assg::Ctl* h_ctl = nullptr;          // pinned mirror
   int32_t* h_status = nullptr;   // pinned
+  int32_t* d_flag = nullptr;     // device flag of the analysis checks
   assg_trace_t* d_trace = nullptr;
   int64_t trace_cap = 0;
   int64_t trace_count = 0;
@@ -29,6 +30,7 @@ struct assg_handle_s {
   // analysis
   int64_t an_n = -1, an_nnz = -1;
   const int32_t* an_rp = nullptr;
+  const int32_t* an_ci = nullptr;
   int32_t* d_blk = nullptr;      // row-block partition (row starts, nonzero starts)
   int32_t* d_blke = nullptr;
   int32_t nblk = 0;
@@ -90,6 +92,8 @@ struct WsLayout {
 WsLayout ws_layout(int64_t n, int32_t s_max);
 assg_status_t fail(assg_handle_t h, assg_status_t st, const std::string& msg);
 bool csr_ok(const assg_csr_t* A);
+// Column indices of A inside [0, n), checked on the device (analysis time).
+assg_status_t check_columns(assg_handle_t h, const int32_t* ci, int64_t nnz, int64_t n);
 assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o);
 void init_ctl(assg_handle_t h, Ctl* c, int mode);
 void apply_variant(Ctl* c, const assg_opts_t* o);

@@ -168,7 +168,7 @@ void launch_setup(hipStream_t s, Ctl* ctl, const CsrView& A, const double* b, co
 // nonzero; levels beyond the loop's s-bar exit at once.
 __global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int level, CsrView A,
                                                double2* __restrict__ pairs, int64_t ld) {
-  __shared__ double prod[2 * SB_CAP];
+  __shared__ __align__(16) double prod[2 * SB_CAP];   // read as double2
   __shared__ double red[4];
   const double2* __restrict__ X = pairs + (size_t)(level - 1) * ld;
   const double2* __restrict__ X2 = pairs + (size_t)(level >= 2 ? level - 2 : 0) * ld;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   constexpr int WR = (W * NB * 256 <= LDS_D) ? W : (W / 2 * NB * 256 <= LDS_D) ? W / 2
                      : (W / 4 * NB * 256 <= LDS_D) ? W / 4 : 1;
   static_assert(WR * NB * 256 <= LDS_D, "accumulator staging exceeds the tile");
-  __shared__ double lds[LDS_D];
+  __shared__ __align__(16) double lds[LDS_D];   // read as double2 (16-byte LDS reads)
   __shared__ double red[W];
   double2* const tile = reinterpret_cast<double2*>(lds);
   double* const prod = lds + TILE_D;
@@ -856,6 +856,25 @@ void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, cons
                           double alpha, double* out) {
   hipLaunchKernelGGL(k_outer_pattern, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, A, u, v,
                      alpha, out);
+}
+
+// *flag = 1 when a column index of ci[0, nnz) lies outside [0, n) (every
+// offending thread stores the same value).
+__global__ __launch_bounds__(256) void k_check_cols(const int32_t* __restrict__ ci, int64_t nnz,
+                                                    int32_t n, int32_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * 256) {
+    const int32_t c = ldnt(ci + e);
+    bad |= (c < 0) | (c >= n);
+  }
+  if (bad) flag[0] = 1;
+}
+
+void launch_check_cols(hipStream_t s, const int32_t* ci, int64_t nnz, int32_t n, int32_t* flag) {
+  const int64_t g = (nnz + 255) / 256;
+  if (g > 0)
+    hipLaunchKernelGGL(k_check_cols, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, ci,
+                       nnz, n, flag);
 }
 
 // dst[i] = src[i] + add (column indices of a system placed in a batch).

@@ -101,6 +101,9 @@ void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, doubl
 void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
                           double alpha, double* out);
 
+// *flag = 1 if some ci[e], e < nnz, is outside [0, n) (flag cleared by the caller).
+void launch_check_cols(hipStream_t s, const int32_t* ci, int64_t nnz, int32_t n, int32_t* flag);
+
 // dst[i] = src[i] + add, i < n (batch assembly).
 void launch_offset_copy(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n, int32_t add);
 
