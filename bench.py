@@ -87,8 +87,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the method's path on one "
-              "GPU's share); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (its path on one GPU's share of the "
+              "rows; sharding across GPUs is not built); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
