@@ -157,13 +157,25 @@ def _check(st, h=None):
         raise AssgError(f"{msg} ({st}): {detail}")
 
 
-def _dptr(t):
+def _dptr(t, numel=None, dtype=None, what="tensor"):
+    """Device pointer of a contiguous CUDA tensor; with ``numel``/``dtype``
+    also checks the element count and type the C ABI will assume (a wrong
+    size would make the kernels read or write past the buffer)."""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a CUDA tensor")
+        raise TypeError(f"{what}: expected a CUDA tensor")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
+
+
+def _f64(t, numel, what):
+    import torch
+    return _dptr(t, numel, torch.float64, what)
 
 
 def _stream_ptr():
@@ -215,8 +227,11 @@ class DeviceCSR:
     nnz: int
 
     def c(self) -> AssgCsr:
-        return AssgCsr(self.n, self.nnz, _dptr(self.row_ptr).value, _dptr(self.col_idx).value,
-                       _dptr(self.val).value)
+        import torch
+        return AssgCsr(self.n, self.nnz,
+                       _dptr(self.row_ptr, self.n + 1, torch.int32, "row_ptr").value,
+                       _dptr(self.col_idx, self.nnz, torch.int32, "col_idx").value,
+                       _dptr(self.val, self.nnz, torch.float64, "val").value)
 
 
 def csr_to_device(A, device="cuda") -> DeviceCSR:
@@ -276,7 +291,8 @@ def assg_solve(h: Handle, A: DeviceCSR, b, x, opts: AssgOpts | None = None, work
     info = AssgInfo()
     d = A.c()
     ws, wsb = (None, 0) if workspace is None else (_dptr(workspace), workspace.numel() * workspace.element_size())
-    _check(lib().assg_solve(h.ptr, C.byref(d), _dptr(b), _dptr(x), C.byref(opts), ws, wsb,
+    _check(lib().assg_solve(h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"),
+                            C.byref(opts), ws, wsb,
                             C.byref(info)), h.ptr)
     return _info_dict(info)
 
@@ -285,7 +301,8 @@ def assg_hscg_solve(h: Handle, A: DeviceCSR, b, x, tol=1e-10, max_iters=0, works
     info = AssgInfo()
     d = A.c()
     ws, wsb = (None, 0) if workspace is None else (_dptr(workspace), workspace.numel() * workspace.element_size())
-    _check(lib().assg_hscg_solve(h.ptr, C.byref(d), _dptr(b), _dptr(x), tol, max_iters, ws, wsb,
+    _check(lib().assg_hscg_solve(h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"), tol,
+                                 max_iters, ws, wsb,
                                  C.byref(info)), h.ptr)
     return _info_dict(info)
 
@@ -305,7 +322,7 @@ def assg_get_trace(h: Handle) -> list:
 
 def assg_spmv(h: Handle, A: DeviceCSR, x, y):
     d = A.c()
-    _check(lib().assg_spmv(h.ptr, C.byref(d), _dptr(x), _dptr(y)), h.ptr)
+    _check(lib().assg_spmv(h.ptr, C.byref(d), _f64(x, A.n, "x"), _f64(y, A.n, "y")), h.ptr)
 
 
 def assg_batch_analyze(h: Handle, As: list):
@@ -322,8 +339,8 @@ def assg_batch_solve(h: Handle, As: list, bs: list, xs: list, opts: AssgOpts | N
         raise ValueError("As, bs and xs must have the same length")
     opts = opts or assg_default_opts()
     arr = (AssgCsr * n)(*[A.c() for A in As])
-    bp = (C.c_void_p * n)(*[_dptr(b).value for b in bs])
-    xp = (C.c_void_p * n)(*[_dptr(x).value for x in xs])
+    bp = (C.c_void_p * n)(*[_f64(b, A.n, f"b[{i}]").value for i, (A, b) in enumerate(zip(As, bs))])
+    xp = (C.c_void_p * n)(*[_f64(x, A.n, f"x[{i}]").value for i, (A, x) in enumerate(zip(As, xs))])
     infos = (AssgInfo * n)()
     _check(lib().assg_batch_solve(h.ptr, n, arr, bp, xp, C.byref(opts), infos), h.ptr)
     return [_info_dict(i) for i in infos]
@@ -342,8 +359,8 @@ def assg_batch_tuning(h: Handle) -> dict:
 def assg_csr_outer_on_pattern(h: Handle, A: DeviceCSR, u, v, alpha: float, out):
     """out[k] = alpha * u[row(k)] * v[col(k)] on A's pattern (CUDA float64)."""
     d = A.c()
-    _check(lib().assg_csr_outer_on_pattern(h.ptr, C.byref(d), _dptr(u), _dptr(v), float(alpha),
-                                           _dptr(out)), h.ptr)
+    _check(lib().assg_csr_outer_on_pattern(h.ptr, C.byref(d), _f64(u, A.n, "u"), _f64(v, A.n, "v"),
+                                           float(alpha), _f64(out, A.nnz, "out")), h.ptr)
 
 
 def assg_basis_gram(h: Handle, A: DeviceCSR, p, r, s: int, theta, gamma, mu, Y_out=None):
@@ -354,8 +371,9 @@ def assg_basis_gram(h: Handle, A: DeviceCSR, p, r, s: int, theta, gamma, mu, Y_o
     mu_ = (C.c_double * MAX_S)(*list(mu)[:max(s - 1, 0)])
     G = (C.c_double * ((2 * s + 1) ** 2))()
     d = A.c()
-    yp = None if Y_out is None else _dptr(Y_out)
-    _check(lib().assg_basis_gram(h.ptr, C.byref(d), _dptr(p), _dptr(r), s, th, ga, mu_, yp, G),
+    yp = None if Y_out is None else _f64(Y_out, (2 * s + 1) * A.n, "Y_out")
+    _check(lib().assg_basis_gram(h.ptr, C.byref(d), _f64(p, A.n, "p"), _f64(r, A.n, "r"), s, th,
+                                 ga, mu_, yp, G),
            h.ptr)
     return np.array(G[:]).reshape(2 * s + 1, 2 * s + 1)
 

@@ -132,3 +132,28 @@ def test_batch_solve_arguments_must_match(env):
     for pr, x in zip(probs, xs):
         xr = x.cpu().numpy()
         assert np.linalg.norm(pr.b - pr.A @ xr) / np.linalg.norm(pr.b) <= 1e-10
+
+
+def test_binding_checks_dtype_and_length(env):
+    """The binding refuses tensors whose type or length differs from what
+    the C ABI assumes, before the library is called."""
+    torch, L, h = env
+    pr, A = _valid(L)
+    L.assg_analyze(h, A)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    opts = L.assg_default_opts(tol=1e-10)
+    with pytest.raises(TypeError):
+        L.assg_solve(h, A, b.float(), x, opts)
+    with pytest.raises(ValueError):
+        L.assg_solve(h, A, b, x[:-1].contiguous(), opts)
+    with pytest.raises(ValueError):
+        L.assg_solve(h, A, b, x[::2], opts)
+    with pytest.raises(TypeError):
+        L.assg_solve(h, _with(L, A, col_idx=A.col_idx.long()), b, x, opts)
+    with pytest.raises(ValueError):
+        L.assg_spmv(h, A, b, torch.empty(A.n + 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        L.assg_csr_outer_on_pattern(h, A, b, b, 1.0,
+                                    torch.empty(A.nnz - 1, dtype=torch.float64, device="cuda"))
+    assert L.assg_solve(h, A, b, x, opts)["outcome"] == L.CONVERGED
