@@ -183,3 +183,28 @@ def test_controller_replays_oracle_loops(env, basis):
                                            rtol=1e-11)
                 th = nxt["params"][0]
                 np.testing.assert_allclose(np.array(S.theta[:th.size]), th, rtol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["poisson3d_21", "ragged_3001"])
+@pytest.mark.parametrize("s", list(range(1, 17)))
+def test_basis_and_gram_every_s(env, name, s):
+    """Every s = 1..16 has its own instance of the fused last sweep (2s+1
+    columns on the matrix cores in 1, 2 or 3 groups of 16): basis columns
+    and G against the oracle for each, Chebyshev parameters."""
+    torch, L, h = env
+    A = PROBLEMS[name]()
+    n = A.shape[0]
+    Ad = _dev(torch, L, h, A)
+    rng = np.random.default_rng(100 + s)
+    p, r = rng.standard_normal(n), rng.standard_normal(n)
+    prm = O.make_params("chebyshev", s, 0.05, 1.9)
+    Yg = torch.empty((2 * s + 1, n), dtype=torch.float64, device="cuda")
+    Gg = L.assg_basis_gram(h, Ad, torch.from_numpy(p).cuda(), torch.from_numpy(r).cuda(), s,
+                           *prm, Y_out=Yg)
+    Yo = O.sstep_basis(A, p, r, s, prm)[:, interleave_perm(s)]
+    colerr = np.linalg.norm(Yg.cpu().numpy().T - Yo, axis=0) / np.linalg.norm(Yo, axis=0)
+    assert colerr.max() <= 1e-12, colerr
+    Go = Yo.T @ Yo
+    scale = np.sqrt(np.outer(np.diag(Go), np.diag(Go)))
+    assert np.all(np.abs(Gg - Go) <= 1e-12 * scale)
+    assert np.array_equal(Gg, Gg.T)

@@ -72,6 +72,26 @@ def test_solve_matches_oracle(env, name, basis, sigma):
     assert sum(t["sk"] for t in tr) == ig["total_iters"]
 
 
+@pytest.mark.parametrize("name", ["poisson2d_45", "diffusion27_14"])
+@pytest.mark.parametrize("sigma", [2, 7, 12, 16])
+def test_solve_matches_oracle_other_sigma(env, name, sigma):
+    """sigma = 2, 7, 12 and the largest supported, 16 (Chebyshev): the same
+    bar as above on the fused kernel's other column counts."""
+    torch, L, h = env
+    pr = _problem(name)
+    tol = 1e-10
+    kw = dict(s_max=sigma, tol=tol, basis="chebyshev")
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    xg, ig = _solve_gpu(torch, L, h, pr, s_init=sigma, growth=sigma, **kw)
+    assert io["outcome"] == O.Outcome.CONVERGED
+    assert ig["outcome"] == L.CONVERGED, ig
+    assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= tol
+    if abs(ig["outer_iters"] - io["outer"]) > 1:
+        lo, hi = oracle_outer_spread(pr, **kw)
+        assert lo - 1 <= ig["outer_iters"] <= hi + 1, (ig["outer_iters"], io["outer"], lo, hi)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+
+
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_24", "diffusion27_14"])
 def test_hscg_matches_oracle(env, name):
     torch, L, h = env
