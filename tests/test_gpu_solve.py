@@ -239,3 +239,51 @@ def test_cfg1_trace_matches_golden(env):
     for t, r in zip(tr, rows):
         assert (t["k"], t["sbar"], t["stilde"], t["sk"]) == tuple(int(v) for v in r[:4])
         assert abs(t["relres_updated"] - float(r[4])) <= 1e-8 * float(r[4])
+
+
+def _tiny(name):
+    rng = np.random.default_rng({"n1": 1, "n2": 2, "n3": 3, "n7": 7, "diag40": 40}[name])
+    if name == "n1":
+        A = np.array([[2.0]])
+    elif name == "n2":
+        A = np.array([[2.0, -1.0], [-1.0, 2.0]])
+    elif name == "n3":
+        M = rng.standard_normal((3, 3)); A = M @ M.T + 3.0 * np.eye(3)
+    elif name == "n7":
+        M = rng.standard_normal((7, 7)); A = M @ M.T + 0.1 * np.eye(7)
+    else:
+        A = np.diag(np.linspace(1.0, 100.0, 40))
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    M.indices = M.indices.astype(np.int32)
+    M.indptr = M.indptr.astype(np.int32)
+    n = M.shape[0]
+    return P.Problem(name=name, A=M, b=rng.standard_normal(n), x0=np.zeros(n))
+
+
+@pytest.mark.parametrize("name", ["n1", "n2", "n3", "n7", "diag40"])
+@pytest.mark.parametrize("basis", ["chebyshev", "newton"])
+@pytest.mark.parametrize("sigma", [1, 10])
+def test_tiny_systems_match_oracle(env, name, basis, sigma):
+    """Degenerate sizes (n = 1, 2, 3: the Krylov space is exhausted within
+    the first loop, so most basis columns are dependent), a dense 7 x 7
+    matrix and a 40-row diagonal with spread eigenvalues: outcome, solution
+    and outer loops against the oracle, and HSCG against its oracle."""
+    torch, L, h = env
+    pr = _tiny(name)
+    kw = dict(s_max=sigma, tol=1e-10, basis=basis)
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    xg, ig = _solve_gpu(torch, L, h, pr, s_init=sigma, growth=sigma, **kw)
+    assert io["outcome"] == O.Outcome.CONVERGED
+    assert ig["outcome"] == L.CONVERGED, ig
+    assert abs(ig["outer_iters"] - io["outer"]) <= 1, (ig["outer_iters"], io["outer"])
+    assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+    xh, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
+    Ad = L.csr_to_device(pr.A)
+    L.assg_analyze(h, Ad)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    gh = L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
+    assert gh["outcome"] == L.CONVERGED and abs(gh["total_iters"] - ih["iters"]) <= 1, (gh, ih["iters"])
+    assert np.linalg.norm(x.cpu().numpy() - xh) / np.linalg.norm(xh) <= 1e-8
