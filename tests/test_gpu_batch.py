@@ -129,3 +129,29 @@ def test_batched_workload_full_size(env):
             lo, hi = oracle_outer_spread(pr, s_max=10, tol=1e-10, basis="chebyshev")
             assert lo - 1 <= infos[i]["outer_iters"] <= hi + 1, (pr.name, lo, hi)
         assert np.linalg.norm(xs[i] - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_batch_at_maximum_size(env):
+    """ASSG_MAX_BATCH = 2048 small systems (2D Poisson, sides 2..6, shifted)
+    in one batch: every system converges with true relative residual <= tol
+    recomputed on the host, every 64th against the oracle; one system more
+    is refused."""
+    torch, L, h = env
+    probs = P.make_batch(count=2048, lo=2, hi=6, seed=11)
+    As = [L.csr_to_device(pr.A) for pr in probs]
+    L.assg_batch_analyze(h, As)
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    xs = [torch.from_numpy(pr.x0.copy()).cuda() for pr in probs]
+    infos = L.assg_batch_solve(h, As, bs, xs, L.assg_default_opts(tol=1e-10))
+    for pr, x, ig in zip(probs, xs, infos):
+        assert ig["outcome"] == L.CONVERGED, (pr.name, ig)
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
+    for i in range(0, 2048, 64):
+        pr = probs[i]
+        xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=10, tol=1e-10)
+        assert abs(infos[i]["outer_iters"] - io["outer"]) <= 1, (i, infos[i], io["outer"])
+        xg = xs[i].cpu().numpy()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+    with pytest.raises(L.AssgError, match="nsys"):
+        L.assg_batch_analyze(h, As + As[:1])
