@@ -213,11 +213,12 @@ void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, do
 // Zero source of the direct-to-LDS basis loads for rows past a block.
 __device__ double2 g_zero_rows[64];
 
-// For each row block (<= 256 rows): the source gathers of the block's
-// CSR-stream products are issued first, then its s-bar basis pairs go from
-// HBM straight into a pair-major LDS tile (direct-to-LDS loads, no
-// registers), and one wait covers both.  The products give P_sbar for the
-// block's rows (stored as the tile's level s-bar); then G = Y^T Y is
+// For each row block (<= 256 rows): first the block's CSR-stream products
+// (gathers of P_{sbar-1}, products into an LDS buffer that is the start of
+// the tile, row sums), then its s-bar basis pairs go from HBM straight into
+// a pair-major LDS tile (direct-to-LDS loads, no registers) and P_sbar
+// becomes the tile's level s-bar.  Sharing the buffer keeps the workgroup
+// at 45 KB of LDS (three per CU at s-bar = 10).  G = Y^T Y is then
 // accumulated on the matrix cores: each wave takes 256/W of the block's
 // rows, four rows per v_mfma_f64_16x16x4_f64, for the 16 x 16 blocks
 // (I, J), I <= J, of the columns padded to NG * 16 (columns past 2 sbar + 1
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   constexpr int NG = (NC + 15) / 16;         // 16-column groups
   constexpr int NB = NG * (NG + 1) / 2;      // accumulated 16 x 16 blocks
   constexpr int TILE_D = 2 * NL * TP;        // tile doubles
-  constexpr int LDS_D = TILE_D + SB_CAP;
+  constexpr int LDS_D = TILE_D > SB_CAP ? TILE_D : SB_CAP;   // products alias the tile
   // the waves' accumulators are added WR waves at a time through the LDS
   constexpr int WR = (W * NB * 256 <= LDS_D) ? W : (W / 2 * NB * 256 <= LDS_D) ? W / 2
                      : (W / 4 * NB * 256 <= LDS_D) ? W / 4 : 1;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   __shared__ __align__(16) double lds[LDS_D];   // read as double2 (16-byte LDS reads)
   __shared__ double red[W];
   double2* const tile = reinterpret_cast<double2*>(lds);
-  double* const prod = lds + TILE_D;
+  double* const prod = lds;
   const double* const tcol = lds;            // column c of row r: tcol[2 (c/2 TP + r) + c%2]
   const int s = ctl->sbar;
   const double th = ctl->theta[s - 1];
@@ -259,7 +260,6 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   const double mu = (s >= 2) ? ctl->mu[s - 2] : 0.0;
   const double* __restrict__ xsrc = reinterpret_cast<const double*>(pairs + (size_t)(s - 1) * ld);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = (s + 1) * TP + tid; i < NL * TP; i += NT) tile[i] = make_double2(0.0, 0.0);
   mfma_d4 acc[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) acc[q] = mfma_d4{0.0, 0.0, 0.0, 0.0};
@@ -310,17 +310,32 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
     if (b0 + 1 < b1) bounds(b0 + 1, nxt);
   }
   for (int32_t b = b0; b < b1; ++b) {
-    // the block's source gathers, then its basis pairs (64-row chunks, a
-    // fixed number per wave: levels past sbar and lanes past the block read
-    // zeros), then one wait for both
+    // products first (their LDS buffer is the start of the tile), then the
+    // basis pairs into the tile: a fixed number of 64-row loads per wave
+    // (levels past sbar and lanes past the block read zeros), and every
+    // wave waits for its own before the barrier, so the tile is complete
+    // after it
     const bool fits = cur.ne <= SB_CAP;
-    double gx[K];
+    const bool own = tid < cur.nr;
+    double a = 0.0, unused;
+    if (fits) {
+      if (cur.ne > 0) {
+        double gx[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) gx[k] = 0.0;
-    if (fits && cur.ne > 0) {
+        for (int k = 0; k < K; ++k) gx[k] = xsrc[2 * (int64_t)f.c[k]];
 #pragma unroll
-      for (int k = 0; k < K; ++k) gx[k] = xsrc[2 * (int64_t)f.c[k]];
+        for (int k = 0; k < K; ++k) {
+          const int32_t e = tid + NT * k;
+          if (e < cur.ne) prod[e] = f.a[k] * gx[k];
+        }
+      }
+      __syncthreads();
+      if (own)
+        for (int32_t e = cur.rs; e < cur.re; ++e) a += prod[e];
+    } else {
+      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, cur.e0, cur.ne, red, a, unused);
     }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < NDW; ++j) {
       const int i = wave + j * W;
@@ -334,26 +349,8 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
             2);   // nt: streamed once
       }
     }
-    const bool own = tid < cur.nr;
-    double a = 0.0, unused;
-    if (fits) {
-      // every wave waits for its loads before the barrier, so the tile is
-      // complete after it
-      __builtin_amdgcn_s_waitcnt(0);
-      if (cur.ne > 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const int32_t e = tid + NT * k;
-          if (e < cur.ne) prod[e] = f.a[k] * gx[k];
-        }
-      }
-      __syncthreads();
-      if (own)
-        for (int32_t e = cur.rs; e < cur.re; ++e) a += prod[e];
-    } else {
-      __builtin_amdgcn_s_waitcnt(0);
-      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, cur.e0, cur.ne, red, a, unused);
-    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     if (tid < TS) {
       double y = 0.0;
       if (own) {
@@ -363,6 +360,8 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
         stnt(plast + (int64_t)cur.r0 + tid, y);
       }
       tile[s * TP + tid] = make_double2(y, 0.0);
+      // the top level is not loaded; the products may have left values in it
+      if (s < SMAX) tile[SMAX * TP + tid] = make_double2(0.0, 0.0);
     }
     if (b + 1 < b1) {
       cur = nxt;
@@ -430,7 +429,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
 }
 
 template <int NC>
-constexpr int gram_waves() { return 8; }
+constexpr int gram_waves() { return 4; }
 
 template <int NC>
 static int last_gram_blocks_nc(int cus) {

@@ -80,18 +80,24 @@ def test_fixed_sstep_breaks_down_at_s15(env):
 
 def test_old_adaptive_degrades_at_s15(env):
     """The same workload with Algorithm 2 (monomial basis, c = 1): a regime
-    where rounding steers the run (the oracle needs 9x HSCG's iterations),
-    so only the behaviour is compared: neither side converges in about
-    HSCG's iteration count, while Algorithm 5 does on both."""
+    where rounding steers the run.  HSCG needs 207 iterations; the oracle
+    converges after 1899, and with one extra rounding error per basis entry
+    (12 seeds) it breaks down (5), hits the cap (4) or converges after
+    442-1501 iterations (3); the GPU's summation order is one more such
+    trajectory.  So only the behaviour is compared: the old method either
+    fails or needs clearly more iterations than HSCG (over 1.1x) on both
+    sides, while Algorithm 5 stays within 5% of HSCG's count."""
     torch, L, h = env
     pr = _problem("poisson2d_64")
-    _, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
+    xh, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
     kw = dict(s_max=15, tol=1e-10, variant="old", max_outer=3000)
     _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
-    _, ig = _gpu(torch, L, h, pr, s_init=15, growth=15, **kw)
-    slow = lambda ok, iters: (not ok) or iters > 2 * ih["iters"]
+    xg, ig = _gpu(torch, L, h, pr, s_init=15, growth=15, **kw)
+    slow = lambda ok, iters: (not ok) or iters > 1.1 * ih["iters"]
     assert slow(io["outcome"] == O.Outcome.CONVERGED, io["iters"])
     assert slow(ig["outcome"] == L.CONVERGED, ig["total_iters"]), ig
+    if ig["outcome"] == L.CONVERGED:
+        assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
     _, ii = _gpu(torch, L, h, pr, s_max=15, s_init=15, growth=15, tol=1e-10)
     assert ii["outcome"] == L.CONVERGED and ii["total_iters"] <= 1.05 * ih["iters"]
 
