@@ -57,7 +57,29 @@ def build(verbose: bool = False, extra=()) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_example()
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(PKG, "examples", "poisson2d.c")
+EXAMPLE_BIN = os.path.join(PKG, "examples", "poisson2d")
+CC = os.environ.get("CC", "gcc")
+
+
+def example_cmd(out: str, extra=()) -> list:
+    """Host compiler command for the plain C example (C11, the public header,
+    linked against the built library and the HIP runtime)."""
+    rocm = os.path.dirname(os.path.dirname(HIPCC)) if os.path.isabs(HIPCC) else "/opt/rocm"
+    return [CC, "-O2", "-std=c11", "-Wall", "-Wextra", *extra, "-D__HIP_PLATFORM_AMD__",
+            f"-I{rocm}/include", f"-I{INCLUDE}", EXAMPLE_SRC, "-o", out, f"-L{PKG}", "-lassg",
+            f"-L{rocm}/lib", "-lamdhip64", "-lm", f"-Wl,-rpath,{PKG}"]
+
+
+def build_example(out: str = EXAMPLE_BIN) -> str:
+    r = subprocess.run(example_cmd(out), capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C example failed to build:\n{r.stdout}\n{r.stderr}")
+    return out
 
 
 if __name__ == "__main__":

@@ -67,3 +67,21 @@ def test_host_only_entry_points():
     assert np.all(ga == 1.0) and np.all(mu == 0.0)
     with pytest.raises(L.AssgError):
         L.assg_basis_params("newton", 2.0, 1.0, 3)
+
+
+def test_c_example_compiles_against_the_header(tmp_path):
+    """The public header is ISO C (C99, pedantic, on its own) and the
+    library's exports link from C: the C example builds with warnings as
+    errors (no GPU needed to build)."""
+    import subprocess
+
+    import paper_1908_04081_amd.build as B
+    src = tmp_path / "only_header.c"
+    src.write_text('#include "assg.h"\nint main(void) { return ASSG_OK; }\n')
+    r = subprocess.run([B.CC, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                        f"-I{B.INCLUDE}", str(src), "-o", str(tmp_path / "only_header")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = str(tmp_path / "poisson2d")
+    r = subprocess.run(B.example_cmd(out, extra=("-Werror",)), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
