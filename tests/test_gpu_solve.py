@@ -287,3 +287,33 @@ def test_tiny_systems_match_oracle(env, name, basis, sigma):
     gh = L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
     assert gh["outcome"] == L.CONVERGED and abs(gh["total_iters"] - ih["iters"]) <= 1, (gh, ih["iters"])
     assert np.linalg.norm(x.cpu().numpy() - xh) / np.linalg.norm(xh) <= 1e-8
+
+
+def test_solve_is_ordered_after_the_callers_stream(env):
+    """The right-hand side is written on a side stream (default priority)
+    behind a long matrix product, and the solve is called on that stream
+    without any host synchronization: the library must wait for the
+    stream's work (event ordering), else it would read b = 0."""
+    torch, L, h = env
+    pr = _problem("poisson2d_64")
+    Ad = L.csr_to_device(pr.A)
+    L.assg_analyze(h, Ad)
+    bsrc = torch.from_numpy(pr.b).cuda()
+    b = torch.zeros_like(bsrc)
+    x = torch.zeros_like(bsrc)
+    big = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(side):
+            for _ in range(4):
+                big = big @ big * 1e-2
+            b.copy_(bsrc)
+            L.assg_set_stream(h, side.cuda_stream)
+            info = L.assg_solve(h, Ad, b, x, L.assg_default_opts(tol=1e-10))
+        torch.cuda.synchronize()
+    finally:
+        L.assg_set_stream(h, torch.cuda.current_stream().cuda_stream)
+    xg = x.cpu().numpy()
+    assert info["outcome"] == L.CONVERGED and info["total_iters"] > 10, info
+    assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
