@@ -218,21 +218,21 @@ __device__ double2 g_zero_rows[64];
 // the tile, row sums), then its s-bar basis pairs go from HBM straight into
 // a pair-major LDS tile (direct-to-LDS loads, no registers) and P_sbar
 // becomes the tile's level s-bar.  Sharing the buffer keeps the workgroup
-// at 45 KB of LDS (three per CU at s-bar = 10).  G = Y^T Y is then
-// accumulated on the matrix cores: each wave takes 256/W of the block's
-// rows, four rows per v_mfma_f64_16x16x4_f64, for the 16 x 16 blocks
-// (I, J), I <= J, of the columns padded to NG * 16 (columns past 2 sbar + 1
-// and rows past the block are zero).  The next block's nonzeros and row
+// at 45 KB of LDS (three per CU at s-bar = 10, which the register budget
+// is held to).  G = Y^T Y is then accumulated on the matrix cores, four
+// rows per v_mfma_f64_16x16x4_f64, the block's 4-row groups dealt to the
+// waves in turn (so a block of few long rows still keeps every wave busy),
+// for the 16 x 16 blocks (I, J), I <= J, of the columns padded to NG * 16
+// (columns past 2 sbar + 1 and rows past the block are zero).  The next block's nonzeros and row
 // ranges are fetched before the Gram, and its bounds one block earlier
 // still.  At the end the waves' accumulators are added in wave order and
 // the unique entries written as this chunk's partials.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int W>
-__global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ctls, CsrView A,
-                                                      const double2* __restrict__ pairs,
-                                                      double* __restrict__ plast, int64_t ld,
-                                                      double* __restrict__ partials) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(NC <= 23 ? 3 : 2)))
+void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restrict__ pairs,
+                 double* __restrict__ plast, int64_t ld, double* __restrict__ partials) {
   int32_t b0, b1, sys;
   const int32_t chunk = chunk_of(A, b0, b1, sys);
   const Ctl* ctl = ctls + sys;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
     coff[g] = cin[g] ? 2 * ((c >> 1) * TP) + (c & 1) : 0;
   }
   const int krow = lane >> 4;                // row within a group of four
-  constexpr int RPW = TS / W;                // rows per wave
+  constexpr int RPW = TS / W;                // rows per wave in a full block
 
   // Row-block bounds come through the scalar cache one block ahead (the
   // partition is read-only), so a block's fetch never waits for them.
@@ -300,7 +300,6 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
   constexpr int ND = 4 * SMAX;        // 64-row loads per block
   constexpr int NDW = (ND + W - 1) / W;
   constexpr int K = SB_CAP / NT;
-  const int rlo = wave * RPW;
   RowFetch<NT, SB_CAP> f;
   Rows cur{}, nxt{};
   if (b0 < b1) {
@@ -339,7 +338,9 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
 #pragma unroll
     for (int j = 0; j < NDW; ++j) {
       const int i = wave + j * W;
-      if (ND % W == 0 || i < ND) {
+      // 64-row chunks past the block are not loaded (the Gram stops at the
+      // block's last 4-row group, which lies in a loaded chunk)
+      if ((ND % W == 0 || i < ND) && ((i & 3) << 6) < cur.nr) {
         const int l = i >> 2, row = ((i & 3) << 6) + lane;
         const double2* src =
             (l < s && row < cur.nr) ? pairs + (size_t)l * ld + cur.r0 + row : g_zero_rows + lane;
@@ -363,6 +364,7 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
       // the top level is not loaded; the products may have left values in it
       if (s < SMAX) tile[SMAX * TP + tid] = make_double2(0.0, 0.0);
     }
+    const int nrb = cur.nr;
     if (b + 1 < b1) {
       cur = nxt;
       own_range(cur);
@@ -370,19 +372,24 @@ __global__ __launch_bounds__(64 * W) void k_last_gram(const Ctl* __restrict__ ct
       if (b + 2 < b1) bounds(b + 2, nxt);
     }
     __syncthreads();
-    // Gram on the matrix cores: rows [wave RPW, (wave + 1) RPW), four at a
-    // time (rows past the block are zero in the tile)
+    // Gram on the matrix cores, four rows per step: the block's 4-row groups
+    // are dealt to the waves in turn, up to its last group (rows past the
+    // block within it are zero in the tile), so a short block (many
+    // nonzeros per row) keeps every wave busy
 #pragma unroll
     for (int k = 0; k < RPW / 4; ++k) {
-      double v[NG];
+      const int r = 4 * (wave + k * W);
+      if (r < nrb) {
+        double v[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) v[g] = cin[g] ? tcol[coff[g] + 2 * (rlo + 4 * k + krow)] : 0.0;
-      int q = 0;
+        for (int g = 0; g < NG; ++g) v[g] = cin[g] ? tcol[coff[g] + 2 * (r + krow)] : 0.0;
+        int q = 0;
 #pragma unroll
-      for (int gi = 0; gi < NG; ++gi)
+        for (int gi = 0; gi < NG; ++gi)
 #pragma unroll
-        for (int gj = gi; gj < NG; ++gj, ++q)
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[gi], v[gj], acc[q], 0, 0, 0);
+          for (int gj = gi; gj < NG; ++gj, ++q)
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[gi], v[gj], acc[q], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
