@@ -41,6 +41,15 @@ Comparison variants of Section 5 (``variant``):
   with the current relative residual rho_{j+1};
 * "fixed": fixed s-step CG, monomial basis, s_k = s-bar = sigma in every
   outer loop (no selection, no break); the stopping test is the same.
+
+Pins (tests/pins.py) fix the solve as a whole (HSCG at sigma = 1, the
+monomial basis against HSCG's coefficients, convergence against a dense
+Cholesky solve), the Ritz estimates, the basis recurrences, B, psi and
+c >= 1.  Three decision details are held only to the paper's text, since no
+independent fact separates them from their neighbours and each alternative
+moves an outer-loop count by at most one on the test problems: the index of
+the break test (gamma_{j+1} rather than kappa(Y_{k,j+1})), phi rather than
+the current residual in that test, and eps = 2^-53 rather than 2^-52.
 """
 from __future__ import annotations
 

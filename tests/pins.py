@@ -295,4 +295,18 @@ def pin_sstep_solves():
         assert min(cs) >= 1.0 and max(cs) <= ev[-1] / ev[0]
 
 
+def pin_adaptive_c_at_least_one():
+    """xi >= 1 by its definition (Section 4), so the adaptive c of Algorithm 5
+    never drops below 1.  On a spectrum in [0.5, 0.6] the estimate
+    lambda_max (psi / lambda_min)^(1/2) is about 0.8 in every loop, so this
+    holds only through the max{1, .} of Algorithm 5."""
+    A = P.diagonal_matrix(np.linspace(0.5, 0.6, 200))
+    b = np.random.default_rng(21).standard_normal(200)
+    for basis in ("chebyshev", "newton"):
+        _, info = O.adaptive_sstep_cg(A, b, s_max=10, tol=1e-12, basis=basis)
+        assert info["outcome"] == O.Outcome.CONVERGED
+        cs = [t["c"] for t in info["trace"][1:]]
+        assert len(cs) >= 2 and min(cs) >= 1.0, cs
+
+
 ALL_PINS = [v for k, v in dict(globals()).items() if k.startswith("pin_")]

@@ -124,6 +124,23 @@ def _mut_hscg_beta(mp):
     mp.setattr(O, "hscg", f)
 
 
+def _mut_source(mp, old, new):
+    """Replaces a line of the oracle's s-step loop (for decision rules that
+    are written inline rather than as functions of their own)."""
+    import inspect
+    src = inspect.getsource(OS)
+    assert old in src
+    ns = {"__name__": OS.__name__, "__package__": "oracle", "__file__": OS.__file__}
+    exec(compile(src.replace(old, new), OS.__file__, "exec"), ns)
+    mp.setattr(OS, "adaptive_sstep_cg", ns["adaptive_sstep_cg"])
+    mp.setattr(O, "adaptive_sstep_cg", ns["adaptive_sstep_cg"])
+
+
+def _mut_c_without_max(mp):
+    _mut_source(mp, "c = max(1.0, lmax * math.sqrt(psi / lmin))",
+                "c = lmax * math.sqrt(psi / lmin)")
+
+
 MUTATIONS = {
     "alg3_wrong_zeta": _mut_alg3_wrong_zeta,
     "alg4_coupling_sign": _mut_alg4_sign,
@@ -138,6 +155,7 @@ MUTATIONS = {
     "newton_first_two_swapped": _mut_newton_swap,
     "alpha_without_B": _mut_alpha_without_B,
     "hscg_beta_scaled": _mut_hscg_beta,
+    "c_without_max": _mut_c_without_max,
 }
 
 
