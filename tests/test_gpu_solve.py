@@ -317,3 +317,25 @@ def test_solve_is_ordered_after_the_callers_stream(env):
     xg = x.cpu().numpy()
     assert info["outcome"] == L.CONVERGED and info["total_iters"] > 10, info
     assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
+
+
+@pytest.mark.parametrize("basis", ["chebyshev", "newton"])
+def test_c_clamp_matches_oracle(env, basis):
+    """A spectrum in [0.5, 0.6], where lambda_max (psi / lambda_min)^(1/2) is
+    below 1 in every loop: the device's c is held at 1 by the max{1, .} of
+    Algorithm 5, loop for loop as in the oracle."""
+    torch, L, h = env
+    A = P.diagonal_matrix(np.linspace(0.5, 0.6, 200))
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    b = np.random.default_rng(21).standard_normal(200)
+    pr = P.Problem(name="diag_0.5_0.6", A=A, b=b, x0=np.zeros(200))
+    kw = dict(s_max=10, tol=1e-12, basis=basis)
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, **kw)
+    xg, ig = _solve_gpu(torch, L, h, pr, s_init=10, growth=10, record_trace=1, **kw)
+    assert ig["outcome"] == L.CONVERGED and abs(ig["outer_iters"] - io["outer"]) <= 1, (ig, io)
+    tr = L.assg_get_trace(h)
+    cg = [t["c"] for t in tr[1:]]
+    co = [t["c"] for t in io["trace"][1:]]
+    assert len(cg) >= 2 and all(c == 1.0 for c in cg) and all(c == 1.0 for c in co), (cg, co)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
