@@ -223,10 +223,11 @@ __device__ double2 g_zero_rows[64];
 // rows per v_mfma_f64_16x16x4_f64, the block's 4-row groups dealt to the
 // waves in turn (so a block of few long rows still keeps every wave busy),
 // for the 16 x 16 blocks (I, J), I <= J, of the columns padded to NG * 16
-// (columns past 2 sbar + 1 and rows past the block are zero).  The next block's nonzeros and row
-// ranges are fetched before the Gram, and its bounds one block earlier
-// still.  At the end the waves' accumulators are added in wave order and
-// the unique entries written as this chunk's partials.
+// (columns past 2 sbar + 1 and rows past the block are zero).  The next
+// block's nonzeros and row ranges are fetched before the Gram, and its
+// bounds one block earlier still.  At the end the waves' accumulators are
+// added in wave order and the unique entries written as this chunk's
+// partials.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int W>
@@ -310,10 +311,9 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   }
   for (int32_t b = b0; b < b1; ++b) {
     // products first (their LDS buffer is the start of the tile), then the
-    // basis pairs into the tile: a fixed number of 64-row loads per wave
-    // (levels past sbar and lanes past the block read zeros), and every
-    // wave waits for its own before the barrier, so the tile is complete
-    // after it
+    // basis pairs into the tile in 64-row loads (levels past sbar and lanes
+    // past the block read zeros); every wave waits for its own before the
+    // barrier, so the tile is complete after it
     const bool fits = cur.ne <= SB_CAP;
     const bool own = tid < cur.nr;
     double a = 0.0, unused;
