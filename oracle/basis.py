@@ -69,7 +69,8 @@ def leja_reference_points(count: int) -> np.ndarray:
 # Basis parameters: arrays theta (s), gamma (s), mu (max(s-1, 0))
 # --------------------------------------------------------------------------
 def params_monomial(s: int):
-    """theta = 0, gamma = 1, mu = 0: the monomial basis."""
+    """theta = 0, gamma = 1, mu = 0: the monomial basis of (2.3) (Section 2),
+    used before the first Ritz estimates and by the comparison methods."""
     return np.zeros(s), np.ones(s), np.zeros(max(s - 1, 0))
 
 
@@ -109,6 +110,8 @@ def params_chebyshev(lmin: float, lmax: float, s: int):
 
 
 def make_params(kind: str, s: int, lmin=None, lmax=None):
+    """(theta, gamma, mu) of the recurrence (2.3) for the monomial basis, the
+    Newton basis (2.7) or the Chebyshev basis (2.8) on [lmin, lmax]."""
     if kind == "monomial":
         return params_monomial(s)
     if kind == "newton":
@@ -172,7 +175,8 @@ def change_of_basis(s: int, params) -> np.ndarray:
 
 def sub_indices(sbar: int, l: int) -> np.ndarray:
     """Columns of Y_{k,l} = [P_{k,l}, R_{k,l}] inside Y_{k,sbar} (paper
-    order): P_0..P_l are columns 0..l, R_0..R_{l-1} are sbar+1..sbar+l.
+    order, (2.2) and Section 3): P_0..P_l are columns 0..l, R_0..R_{l-1} are
+    sbar+1..sbar+l.
 
     Reading: the "leading principal submatrices" of G used for kappa(Y_{k,l})
     are the principal submatrices on exactly these columns."""
