@@ -97,8 +97,8 @@ typedef struct {
 /* Inputs of Algorithm 5 besides A, b and x0. */
 typedef struct {
   int32_t s_max;       /* sigma: largest s_k, 1..ASSG_MAX_S (default 10)          */
-  int32_t s_init;      /* s-bar_0, 1..s_max (default s_max)                       */
-  int32_t growth;      /* f >= 1: s-bar_k = min(s_{k-1} + f, sigma) (default s_max) */
+  int32_t s_init;      /* s-bar_0, 1..s_max; 0 (the default) means s_max          */
+  int32_t growth;      /* f >= 1: s-bar_k = min(s_{k-1} + f, sigma); 0 (default): s_max */
   int32_t basis;       /* assg_basis_t (default ASSG_BASIS_CHEBYSHEV)             */
   double tol;          /* eps*: relative residual target, (0, 1) (default 1e-10)  */
   int64_t max_outer;   /* cap on outer loops; 0 -> max_iters                      */

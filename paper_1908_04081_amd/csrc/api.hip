@@ -225,9 +225,9 @@ assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o) {
   if (!o) return fail(h, ASSG_ERR_INVALID_ARG, "null options");
   if (o->s_max < 1 || o->s_max > ASSG_MAX_S)
     return fail(h, ASSG_ERR_INVALID_ARG, "s_max must be in 1..ASSG_MAX_S");
-  if (o->s_init < 1 || o->s_init > o->s_max)
-    return fail(h, ASSG_ERR_INVALID_ARG, "s_init must be in 1..s_max");
-  if (o->growth < 1) return fail(h, ASSG_ERR_INVALID_ARG, "growth must be >= 1");
+  if (o->s_init < 0 || o->s_init > o->s_max)
+    return fail(h, ASSG_ERR_INVALID_ARG, "s_init must be in 1..s_max (0: s_max)");
+  if (o->growth < 0) return fail(h, ASSG_ERR_INVALID_ARG, "growth must be >= 1 (0: s_max)");
   if (o->basis != ASSG_BASIS_MONOMIAL && o->basis != ASSG_BASIS_NEWTON &&
       o->basis != ASSG_BASIS_CHEBYSHEV)
     return fail(h, ASSG_ERR_INVALID_ARG, "unknown basis");
@@ -250,8 +250,8 @@ assg_status_t assg_default_opts(assg_opts_t* o) {
   if (!o) return ASSG_ERR_INVALID_ARG;
   std::memset(o, 0, sizeof(*o));
   o->s_max = 10;
-  o->s_init = 10;
-  o->growth = 10;
+  o->s_init = 0;   // s-bar_0 = sigma
+  o->growth = 0;   // f = sigma
   o->basis = ASSG_BASIS_CHEBYSHEV;
   o->tol = 1e-10;
   o->max_outer = 0;
@@ -488,10 +488,10 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
 
   Ctl* c = h->h_ctl;
   init_ctl(h, c, 0);
-  c->sbar = opts->s_init;
-  c->sbar_next = opts->s_init;
+  c->sbar = opts->s_init > 0 ? opts->s_init : opts->s_max;
+  c->sbar_next = c->sbar;
   c->sigma = sigma;
-  c->growth = opts->growth;
+  c->growth = opts->growth > 0 ? opts->growth : opts->s_max;
   c->basis = opts->basis;
   c->record_trace = opts->record_trace ? 1 : 0;
   c->trace_cap = opts->record_trace ? h->trace_cap : 0;

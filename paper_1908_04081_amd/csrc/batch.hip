@@ -298,10 +298,10 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
     Ctl* c = B.hctl + i;
     init_ctl(h, c, 0);
     const int64_t max_iters = opts->max_iters > 0 ? opts->max_iters : 10 * B.n[i];
-    c->sbar = opts->s_init;
-    c->sbar_next = opts->s_init;
+    c->sbar = opts->s_init > 0 ? opts->s_init : opts->s_max;
+    c->sbar_next = c->sbar;
     c->sigma = sigma;
-    c->growth = opts->growth;
+    c->growth = opts->growth > 0 ? opts->growth : opts->s_max;
     c->basis = opts->basis;
     c->record_trace = 0;
     c->max_outer = opts->max_outer > 0 ? opts->max_outer : max_iters;

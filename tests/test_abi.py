@@ -54,7 +54,7 @@ def test_host_only_entry_points():
     L, lib = _lib()
     o = L.assg_default_opts()
     assert (o.s_max, o.s_init, o.growth, o.basis, o.tol, o.variant, o.c_const) == \
-        (10, 10, 10, 2, 1e-10, 0, 1.0)
+        (10, 0, 0, 2, 1e-10, 0, 1.0)   # s_init = growth = 0: both follow s_max
     assert lib.assg_status_string(0) == b"ok"
     assert L.assg_workspace_size(1000, 10) > 21 * 1000 * 8
     # Chebyshev (2.8) as read here: theta = centre, gamma_0 = d/2, gamma_l = mu_l = d/4

@@ -161,7 +161,8 @@ def test_max_outer(env):
 def test_bad_options_rejected(env):
     torch, L, h = env
     pr = _problem("poisson2d_45")
-    for bad in ({"s_max": 0}, {"s_max": 17}, {"s_init": 11}, {"growth": 0}, {"tol": 0.0},
+    for bad in ({"s_max": 0}, {"s_max": 17}, {"s_init": 11}, {"s_init": -1}, {"growth": -1},
+                {"tol": 0.0},
                 {"tol": 1.5}, {"basis": 7}):
         with pytest.raises(L.AssgError):
             _solve_gpu(torch, L, h, pr, **bad)
@@ -339,3 +340,21 @@ def test_c_clamp_matches_oracle(env, basis):
     co = [t["c"] for t in io["trace"][1:]]
     assert len(cg) >= 2 and all(c == 1.0 for c in cg) and all(c == 1.0 for c in co), (cg, co)
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_defaults_follow_s_max(env):
+    """s_init and growth left at their defaults follow s_max (s-bar_0 = f =
+    sigma, as in the oracle), for the single and the batched solve."""
+    torch, L, h = env
+    pr = _problem("poisson2d_45")
+    xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=7, tol=1e-10)
+    xg, ig = _solve_gpu(torch, L, h, pr, s_max=7, tol=1e-10, record_trace=1)
+    tr = L.assg_get_trace(h)
+    assert [t["sbar"] for t in tr[:3]] == [r["sbar"] for r in io["trace"][:3]] == [7, 7, 7]
+    assert abs(ig["outer_iters"] - io["outer"]) <= 1
+    Ad = L.csr_to_device(pr.A)
+    L.assg_batch_analyze(h, [Ad])
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    (ib,) = L.assg_batch_solve(h, [Ad], [b], [x], L.assg_default_opts(s_max=7, tol=1e-10))
+    assert ib["outcome"] == L.CONVERGED and abs(ib["outer_iters"] - io["outer"]) <= 1
