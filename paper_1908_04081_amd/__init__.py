@@ -185,9 +185,14 @@ def _stream_ptr():
 
 # ----------------------------------------------------------------- host-only
 def assg_default_opts(**overrides) -> AssgOpts:
+    """The library's default options with the given fields replaced; an
+    unknown field name raises TypeError (a typo would otherwise be ignored)."""
     o = AssgOpts()
     _check(lib().assg_default_opts(C.byref(o)))
+    names = {f for f, _ in AssgOpts._fields_ if not f.startswith("pad")}
     for k, v in overrides.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r}; options: {sorted(names)}")
         if k == "basis" and isinstance(v, str):
             v = BASIS[v]
         if k == "variant" and isinstance(v, str):

@@ -85,3 +85,10 @@ def test_c_example_compiles_against_the_header(tmp_path):
     out = str(tmp_path / "poisson2d")
     r = subprocess.run(B.example_cmd(out, extra=("-Werror",)), capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_unknown_option_is_refused():
+    L, _ = _lib()
+    with pytest.raises(TypeError):
+        L.assg_default_opts(smax=5)
+    assert L.assg_default_opts(s_max=5).s_max == 5
