@@ -238,7 +238,7 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
 
 /* Algorithm 5: improved adaptive s-step CG (or a comparison method, see
  * opts.variant).  b (device, n) is read; x (device, n) holds x0 on entry and
- * the solution on return.  ``workspace`` (device, >= assg_workspace_size
+ * the solution on return; b and x must not overlap (ASSG_ERR_INVALID_ARG).  ``workspace`` (device, >= assg_workspace_size
  * bytes) may be NULL, in which case the handle allocates and keeps one.
  * info (host) receives the outcome and iteration counts.  The relative
  * residual is ||b - A x|| / ||b||; with b = 0 the result is x = 0,
@@ -318,7 +318,7 @@ assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, co
 
 /* ------------------------------------------ single steps of the hot path */
 
-/* y = A x (device x, y; n each). */
+/* y = A x (device x, y; n each; x and y must not overlap). */
 assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, double* y);
 
 /* The basis and Gram matrix of one outer loop with given parameters:

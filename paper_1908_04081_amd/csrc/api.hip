@@ -428,6 +428,7 @@ assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, d
   if (!h || !x || !y) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
+  if (overlap(x, y, A->n)) return fail(h, ASSG_ERR_INVALID_ARG, "x and y overlap");
   const CsrView Av = view(h, A);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
@@ -461,6 +462,7 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   if (st != ASSG_OK) return st;
   st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
+  if (overlap(b, x, A->n)) return fail(h, ASSG_ERR_INVALID_ARG, "b and x overlap");
   std::memset(info, 0, sizeof(*info));
   const int64_t n = A->n;
   const int sigma = opts->s_max;
@@ -642,6 +644,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
     return fail(h, ASSG_ERR_INVALID_ARG, "tol must be in (0,1), max_iters >= 0");
   assg_status_t st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
+  if (overlap(b, x, A->n)) return fail(h, ASSG_ERR_INVALID_ARG, "b and x overlap");
   std::memset(info, 0, sizeof(*info));
   const int64_t n = A->n;
   char* base = nullptr;

@@ -92,6 +92,12 @@ struct WsLayout {
 WsLayout ws_layout(int64_t n, int32_t s_max);
 assg_status_t fail(assg_handle_t h, assg_status_t st, const std::string& msg);
 bool csr_ok(const assg_csr_t* A);
+// True when the n-element vectors at a and b share any element.
+inline bool overlap(const double* a, const double* b, int64_t n) {
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  const uintptr_t len = static_cast<uintptr_t>(n) * sizeof(double);
+  return pa < pb + len && pb < pa + len;
+}
 // Column indices of A inside [0, n), checked on the device (analysis time).
 assg_status_t check_columns(assg_handle_t h, const int32_t* ci, int64_t nnz, int64_t n);
 assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o);

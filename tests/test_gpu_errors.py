@@ -157,3 +157,21 @@ def test_binding_checks_dtype_and_length(env):
         L.assg_csr_outer_on_pattern(h, A, b, b, 1.0,
                                     torch.empty(A.nnz - 1, dtype=torch.float64, device="cuda"))
     assert L.assg_solve(h, A, b, x, opts)["outcome"] == L.CONVERGED
+
+
+def test_overlapping_vectors_refused(env):
+    """b and x (and the SpMV's x and y) must not share memory: the library
+    reads one while it writes the other."""
+    torch, L, h = env
+    pr, A = _valid(L)
+    L.assg_analyze(h, A)
+    buf = torch.zeros(2 * A.n, dtype=torch.float64, device="cuda")
+    b = buf[:A.n]
+    with pytest.raises(L.AssgError, match="overlap"):
+        L.assg_solve(h, A, b, b, L.assg_default_opts(tol=1e-10))
+    with pytest.raises(L.AssgError, match="overlap"):
+        L.assg_hscg_solve(h, A, b, buf[1:A.n + 1], 1e-10, 0)
+    with pytest.raises(L.AssgError, match="overlap"):
+        L.assg_spmv(h, A, b, b)
+    y = buf[A.n:]
+    L.assg_spmv(h, A, b, y)                                # adjacent, not overlapping
