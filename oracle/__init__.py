@@ -28,12 +28,12 @@ from .ritz import (lanczos_tridiagonal, lanczos_cholesky_factor, MaxRitzEstimate
 from .basis import (leja_reference_points, params_monomial, params_newton,
                     params_chebyshev, make_params, polynomial_columns, sstep_basis,
                     change_of_basis, sub_indices)
-from .sstep import adaptive_sstep_cg, UNIT_ROUNDOFF, Outcome
+from .sstep import adaptive_sstep_cg, select_stilde, UNIT_ROUNDOFF, Outcome
 
 __all__ = [
     "hscg", "lanczos_tridiagonal", "lanczos_cholesky_factor", "MaxRitzEstimate",
     "MinRitzEstimate", "psi_update", "leja_reference_points", "params_monomial",
     "params_newton", "params_chebyshev", "make_params", "polynomial_columns",
-    "sstep_basis", "change_of_basis", "sub_indices", "adaptive_sstep_cg",
+    "sstep_basis", "change_of_basis", "sub_indices", "adaptive_sstep_cg", "select_stilde",
     "UNIT_ROUNDOFF", "Outcome",
 ]

@@ -45,11 +45,14 @@ Comparison variants of Section 5 (``variant``):
 Pins (tests/pins.py) fix the solve as a whole (HSCG at sigma = 1, the
 monomial basis against HSCG's coefficients, convergence against a dense
 Cholesky solve), the Ritz estimates, the basis recurrences, B, psi and
-c >= 1.  Three decision details are held only to the paper's text, since no
-independent fact separates them from their neighbours and each alternative
-moves an outer-loop count by at most one on the test problems: the index of
-the break test (gamma_{j+1} rather than kappa(Y_{k,j+1})), phi rather than
-the current residual in that test, and eps = 2^-53 rather than 2^-52.
+c >= 1, and the adaptive control of each run against quantities computed
+without this code: kappa against an SVD of the recorded basis, the
+relative-residual reading by exact power-of-two scaling of b, the Ritz
+estimates after every inner step against explicit Rayleigh-Ritz problems on
+T, psi and c against the recovered vectors, the basis of every loop against
+the Chebyshev closed form of the previous loop's estimates, every (4.7)
+decision of a run where the break fires in many loops (index, phi and
+eps = 2^-53 included), and the first-failure rule of the s~ scan.
 """
 from __future__ import annotations
 
@@ -62,6 +65,25 @@ from .outcome import Outcome
 from .ritz import MaxRitzEstimate, MinRitzEstimate, psi_update
 
 UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def select_stilde(kappa, thr) -> int:
+    """s~ of (3.2): the largest l in 1..sbar for which kappa(Y_{k,l}) <=
+    thr (``kappa[l-1]`` = kappa(Y_{k,l})).
+
+    Reading: the scan runs upward and stops at the first l that fails, with
+    s~ >= 1 even when l = 1 fails.  Y_{k,l} is a column subset of
+    Y_{k,l+1}, so by interlacing kappa(Y_{k,l}) is nondecreasing in l in
+    exact arithmetic and this is the largest passing l; computed values can
+    break that order only through rounding on a numerically singular G, and
+    then no sub-basis past the first failure is taken."""
+    stilde = 1
+    for l in range(1, len(kappa) + 1):
+        if kappa[l - 1] <= thr:
+            stilde = l
+        else:
+            break
+    return stilde
 
 
 def _kappa_sub(G, idx) -> float:
@@ -79,7 +101,8 @@ VARIANTS = ("improved", "improved_c_ratio", "improved_c_one", "old", "fixed")
 
 def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-10,
                       basis="chebyshev", max_outer=None, max_iters=None, record=True,
-                      record_gram=False, variant="improved", c_const=1.0):
+                      record_gram=False, record_basis=False, variant="improved",
+                      c_const=1.0):
     """Solve A x = b by the improved adaptive s-step CG (Algorithm 5).
 
     Parameters follow the algorithm's inputs: sigma = ``s_max``,
@@ -87,8 +110,10 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
     eps* = ``tol``; ``basis`` is "chebyshev", "newton" or "monomial" (the
     last keeps the monomial basis throughout).
     Returns (x, info); ``info["trace"]`` has one record per outer loop.
-    With ``record_gram`` each record also keeps G (paper order) and the
-    carried state at the start of the loop (for step-by-step comparisons).
+    With ``record_gram`` each record also keeps G (paper order), the carried
+    state at the start of the loop and, per inner step, the scalars and the
+    coordinate vectors after the step (for step-by-step comparisons); with
+    ``record_basis`` it keeps the basis Y itself (small problems only).
     """
     if variant not in VARIANTS:
         raise ValueError(f"unknown variant {variant!r}")
@@ -134,8 +159,11 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
         Y = sstep_basis(A, p, r, sbar, params)
         G = Y.T @ Y
         rec = {"k": k, "sbar": sbar, "m": m, "c_in": c}
+        if record_basis:
+            rec["Y"] = Y.copy()
         if record_gram:
             rec["G"] = G.copy()
+            rec["steps"] = []
             rec["state_in"] = {
                 "m": m, "c": c, "psi": psi, "alpha_prev": alpha_prev, "beta_prev": beta_prev,
                 "mt_max": None if mt_max is None else (mt_max.omega, mt_max.h, mt_max.zeta),
@@ -152,12 +180,7 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
         rho_m = math.sqrt(max(G[r_idx, r_idx], 0.0)) / nb
         thr = tol / (c * u * rho_m) if rho_m > 0.0 else math.inf
         kappa = [math.nan] + [_kappa_sub(G, sub_indices(sbar, l)) for l in range(1, sbar + 1)]
-        stilde = 1
-        for l in range(1, sbar + 1):
-            if kappa[l] <= thr:
-                stilde = l
-            else:
-                break
+        stilde = select_stilde(kappa[1:], thr)
         if variant == "fixed":
             stilde = sbar
         gam = {l: kappa[l + 1] for l in range(1, stilde)}
@@ -171,6 +194,7 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
         rGr = max(float(rc @ Gs @ rc), 0.0)
         phi = math.sqrt(rGr) / nb
         candidate = False
+        broke = False
         sk = 0
         rec.update(thr=thr, kappa=kappa[1:], stilde=stilde, rho_m=rho_m)
         for j in range(stilde):
@@ -211,6 +235,10 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
             alpha_prev, beta_prev = alpha, beta
             info["alphas"].append(alpha)
             info["betas"].append(beta)
+            if record_gram:
+                rec["steps"].append({"alpha": alpha, "beta": beta, "rho": rho, "phi": phi,
+                                     "psi": psi, "c": c, "lmin": lmin, "lmax": lmax,
+                                     "rc": rc.copy(), "pc": pc.copy()})
             if not (np.isfinite(alpha) and np.isfinite(beta)):
                 outcome = Outcome.DIVERGED
                 break
@@ -219,12 +247,14 @@ def adaptive_sstep_cg(A, b, x0=None, s_max=10, s_init=None, growth=None, tol=1e-
                 break
             if improved:
                 if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):   # (4.7)
+                    broke = True
                     break
             elif variant == "old":
                 if j < stilde - 1 and kappa[stilde] >= tol / (c * u * rho):
+                    broke = True
                     break
         rec.update(sk=sk, phi=phi, c=c, lmin=lmin, lmax=lmax, psi=psi,
-                   relres_updated=math.sqrt(rGr) / nb, candidate=candidate)
+                   relres_updated=math.sqrt(rGr) / nb, candidate=candidate, broke=broke)
         if record_gram:
             rec.update(xc=xc.copy(), rc=rc.copy(), pc=pc.copy(),
                        alphas=info["alphas"][m:m + sk], betas=info["betas"][m:m + sk])

@@ -309,4 +309,227 @@ def pin_adaptive_c_at_least_one():
         assert len(cs) >= 2 and min(cs) >= 1.0, cs
 
 
+
+# ------------------------------------------------- adaptive control (a4, a5)
+# These pins hold the wiring of Algorithm 5 (which quantities feed (3.2),
+# (4.5)-(4.7) and the basis update) to facts computed independently of the
+# oracle's code: condition numbers from an SVD of the recorded basis, the
+# Ritz estimates from explicit 2x2 Rayleigh-Ritz problems on T of (1.1),
+# psi and the residual norms from the recovered vectors, the basis from the
+# Chebyshev closed form on a diagonal matrix.
+
+U = 2.0 ** -53
+
+
+def _geom_problem(n=100, cond=1e4, seed=1):
+    """Diagonal SPD matrix with a geometric spectrum in [2/cond, 2]: CG's
+    residual norm oscillates, so the break (4.7) fires in several loops."""
+    vals = np.geomspace(1.0 / cond, 1.0, n) * 2.0
+    A = P.diagonal_matrix(vals)
+    b = np.random.default_rng(seed).standard_normal(n)
+    return A, b, vals
+
+
+def _recorded_run(A, b, **kw):
+    x, info = O.adaptive_sstep_cg(A, b, record_gram=True, record_basis=True, **kw)
+    assert info["outcome"] == O.Outcome.CONVERGED, info["outcome"]
+    return x, info
+
+
+def _svd_cond(Y):
+    sv = np.linalg.svd(Y, compute_uv=False)
+    return sv[0] / sv[-1] if sv[-1] > 0 else math.inf
+
+
+def pin_kappa_is_basis_condition_number():
+    """Section 3: kappa(Y_{k,l}) is estimated as the square root of the
+    condition number of the matching principal submatrix of G.  Every
+    recorded kappa of a run whose basis is well enough conditioned for the
+    estimate to be accurate (kappa(Y) < 1e5) equals the 2-norm condition
+    number of the recorded basis columns, from an SVD."""
+    A, b, _ = _geom_problem()
+    _, info = _recorded_run(A, b, s_max=10, tol=1e-10, basis="chebyshev")
+    checked = 0
+    for rec in info["trace"][2:]:
+        Y, sbar = rec["Y"], rec["sbar"]
+        for l in range(1, sbar + 1):
+            ref = _svd_cond(Y[:, O.sub_indices(sbar, l)])
+            if ref < 1e5:
+                got = rec["kappa"][l - 1]
+                assert abs(got - ref) <= 1e-6 * ref, (rec["k"], l, got, ref)
+                checked += 1
+    assert checked > 100, checked
+
+
+def pin_relative_residual_scale_invariance():
+    """eps* is a relative tolerance (Section 3), and (3.2) and (4.7) compare
+    against relative residual norms: scaling b by 2^20 or 2^-20 (exact in
+    binary floating point) scales every vector of the run and leaves every
+    decision, hence s~, s_k and the outer-loop count, unchanged."""
+    cases = [(_geom_problem()[:2], dict(s_max=10, basis="chebyshev")),
+             ((P.poisson2d(20), np.random.default_rng(31).standard_normal(400)),
+              dict(s_max=10, basis="newton"))]
+    for (A, b), kw in cases:
+        ref = None
+        for scale in (1.0, 2.0 ** 20, 2.0 ** -20):
+            _, info = O.adaptive_sstep_cg(A, b * scale, tol=1e-10, **kw)
+            sched = [(t["sbar"], t["stilde"], t["sk"]) for t in info["trace"]]
+            if ref is None:
+                ref = (info["outer"], sched)
+                assert any(st < kw["s_max"] for _, st, _ in sched[2:])   # thr matters
+            else:
+                assert (info["outer"], sched) == ref, scale
+
+
+def _rayleigh_ritz_extremes(alphas, betas, nsteps):
+    """Brute force for Algorithms 3 and 4: explicit unit vectors and dense
+    2x2 eigenproblems on T of (1.1) (largest) and on L^{-1} L^{-T} of (4.1)
+    (whose largest eigenvalue is 1 / lambda_min(T)), bordered one row at a
+    time."""
+    T = O.lanczos_tridiagonal(alphas, betas, nsteps + 1)
+    Lt = O.lanczos_cholesky_factor(alphas, betas, nsteps + 1)
+    hi = _explicit_rayleigh_ritz(lambda k: T[:k, :k], nsteps)
+
+    def inv_gram(k):
+        W = np.linalg.inv(Lt[:k, :k].T)
+        return W @ W.T
+    lo = _explicit_rayleigh_ritz(inv_gram, nsteps)
+    return np.array(hi), 1.0 / np.array(lo)
+
+
+def pin_ritz_estimates_follow_the_run():
+    """Algorithm 5 updates the estimates after global iteration i = m + j
+    whenever i >= 1, from T_{i+1} built with the run's own alpha_0..alpha_i
+    and beta_0..beta_{i-1}: the recorded lambda~max / lambda~min after each
+    inner step equal explicit Rayleigh-Ritz values on that T."""
+    A, b, _ = _geom_problem()
+    _, info = _recorded_run(A, b, s_max=10, tol=1e-10, basis="chebyshev")
+    steps = [st for rec in info["trace"] for st in rec["steps"]]
+    nchk = 60
+    hi, lo = _rayleigh_ritz_extremes(info["alphas"], info["betas"], nchk)
+    assert math.isnan(steps[0]["lmax"]) and math.isnan(steps[0]["lmin"])
+    for i in range(1, nchk + 1):
+        assert abs(steps[i]["lmax"] - hi[i - 1]) <= 1e-10 * hi[i - 1], (i, steps[i]["lmax"], hi[i - 1])
+        assert abs(steps[i]["lmin"] - lo[i - 1]) <= 1e-8 * lo[i - 1], (i, steps[i]["lmin"], lo[i - 1])
+
+
+def pin_adaptive_c_follows_the_run():
+    """(4.5)/(4.6) in the run: after every inner step the recorded psi equals
+    ||r||^2 / ||p||^2 of the vectors Y r', Y p' of that step, and c equals
+    max{1, lambda~max (psi / lambda~min)^(1/2)} with those estimates (the
+    estimates themselves are pinned above); on this spectrum c is far above
+    1, so both the estimates' roles and the max are exercised.  The identity
+    behind (4.5) needs r_{i+1} orthogonal to p_i, which rounding erodes as
+    the solve goes on (at kappa(A) = 1e4 the drift is ~1e-7 over the first
+    150 iterations checked here and ~1e-6 by iteration 270), hence the 1e-5
+    tolerance."""
+    A, b, _ = _geom_problem()
+    _, info = _recorded_run(A, b, s_max=10, tol=1e-10, basis="chebyshev")
+    checked = 0
+    for rec in info["trace"][1:]:
+        Ys = rec["Y"][:, O.sub_indices(rec["sbar"], rec["stilde"])]
+        if _svd_cond(Ys) > 1e5 or rec["m"] >= 150:
+            continue
+        for st in rec["steps"]:
+            r, pv = Ys @ st["rc"], Ys @ st["pc"]
+            psi = float(r @ r) / float(pv @ pv)
+            assert abs(st["psi"] - psi) <= 1e-5 * psi, (rec["k"], st["psi"], psi)
+            xi = st["lmax"] * math.sqrt(psi / st["lmin"])
+            assert xi > 2.0
+            assert abs(st["c"] - max(1.0, xi)) <= 1e-5 * xi, (rec["k"], st["c"], xi)
+            checked += 1
+    assert checked > 40, checked
+
+
+def pin_basis_follows_ritz_estimates():
+    """Algorithm 5 regenerates the basis parameters from the latest estimates
+    after every loop once m > 1: on a diagonal A the P columns of loop k are
+    T_l(2 (z - theta)/Delta) p with theta, Delta from the estimates at the
+    end of loop k-1 (numpy's chebval); on the 2-D Poisson matrix the
+    resulting basis is far better conditioned than the monomial basis built
+    from the same p and r."""
+    A, b, z = _geom_problem()
+    _, info = _recorded_run(A, b, s_max=10, tol=1e-10, basis="chebyshev")
+    tr = info["trace"]
+    checked = 0
+    for k in range(1, len(tr)):
+        if tr[k]["m"] <= 1:
+            continue
+        lo, hi = tr[k - 1]["lmin"], tr[k - 1]["lmax"]
+        Y, sbar = tr[k]["Y"], tr[k]["sbar"]
+        p = Y[:, 0]
+        t = 2.0 * (z - 0.5 * (lo + hi)) / (hi - lo)
+        for l in range(sbar + 1):
+            ref = npcheb.chebval(t, np.eye(sbar + 1)[l]) * p
+            assert np.linalg.norm(Y[:, l] - ref) <= 1e-9 * np.linalg.norm(ref), (k, l)
+        checked += 1
+    assert checked > 50
+    A = P.poisson2d(20)
+    b = np.random.default_rng(31).standard_normal(400)
+    _, info = _recorded_run(A, b, s_max=10, tol=1e-10, basis="chebyshev")
+    # before m reaches sbar, [P, R] spans K_{m+sbar+1}(A, r_0) with 2 sbar + 1
+    # columns and is singular for any polynomials
+    late = [rec for rec in info["trace"] if rec["sbar"] == 10 and rec["m"] >= 10]
+    assert len(late) >= 5
+    for rec in late:
+        Y = rec["Y"]
+        mono = O.sstep_basis(A, Y[:, 0], Y[:, 11], 10, O.params_monomial(10))
+        assert _svd_cond(Y) < 1e-3 * _svd_cond(mono), (rec["k"], _svd_cond(Y), _svd_cond(mono))
+
+
+def pin_break_rule_4_7():
+    """(4.7) as Algorithm 5 writes it: after inner step j < s~-1 the loop
+    ends exactly when kappa(Y_{k,j+2}) >= eps* / (c_{m+j+1} eps phi), phi the
+    largest relative residual norm of the loop so far.  Every decision of a
+    run on a spectrum where this fires in several loops is recomputed with
+    kappa from an SVD of the recorded basis and phi from the norms of the
+    recovered residual vectors (decisions within 1e-4 of the threshold are
+    skipped: there the two computations may legitimately differ)."""
+    A, b, _ = _geom_problem()
+    for kw in (dict(s_max=10, basis="chebyshev"), dict(s_max=15, basis="newton")):
+        _, info = _recorded_run(A, b, tol=1e-10, **kw)
+        nb = float(np.linalg.norm(b))
+        verified_breaks = 0
+        for rec in info["trace"]:
+            st, sbar = rec["stilde"], rec["sbar"]
+            Ys = rec["Y"][:, O.sub_indices(sbar, st)]
+            phi = np.linalg.norm(rec["Y"][:, sbar + 1]) / nb
+            for j, step in enumerate(rec["steps"]):
+                phi = max(phi, np.linalg.norm(Ys @ step["rc"]) / nb)
+                if j >= st - 1 or step["rho"] <= 1e-10:
+                    continue
+                gamma = _svd_cond(rec["Y"][:, O.sub_indices(sbar, j + 2)])
+                thr = 1e-10 / (step["c"] * U * phi)
+                if abs(gamma / thr - 1.0) < 1e-4 + 16 * U * gamma * gamma:
+                    continue
+                broke_here = rec["broke"] and j == rec["sk"] - 1
+                assert (gamma >= thr) == broke_here, (rec["k"], j, gamma, thr, rec["sk"])
+                verified_breaks += broke_here
+        assert verified_breaks >= 5, verified_breaks
+
+
+def pin_stilde_is_first_failure():
+    """(3.2): s~ is the largest l whose basis passes; kappa(Y_{k,l}) is
+    nondecreasing in l in exact arithmetic (interlacing), so on monotone
+    values this is the paper's literal maximum, at least 1.  On values whose
+    order rounding has broken (a numerically singular G reporting kappa = inf
+    before a finite value), no basis past the first failure is taken, so
+    every sub-basis the inner loop uses passes (3.2).  Runs obey the same:
+    every kappa(Y_{k,l}), l <= s~, passes whenever s~ > 1."""
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        kap = np.sort(10.0 ** rng.uniform(0, 8, rng.integers(1, 17)))
+        thr = 10.0 ** rng.uniform(0, 8)
+        passing = [l for l in range(1, kap.size + 1) if kap[l - 1] <= thr]
+        assert O.select_stilde(list(kap), thr) == (max(passing) if passing else 1)
+    assert O.select_stilde([2.0, 5.0, math.inf, 3.0, 4.0], 10.0) == 2
+    assert O.select_stilde([2.0, 50.0, 3.0], 10.0) == 1
+    assert O.select_stilde([math.inf, 1.0], 10.0) == 1
+    A, b, _ = _geom_problem()
+    _, info = O.adaptive_sstep_cg(A, b, s_max=15, tol=1e-10, basis="newton")
+    for rec in info["trace"]:
+        if rec["stilde"] > 1:
+            assert all(kp <= rec["thr"] for kp in rec["kappa"][:rec["stilde"]]), rec["k"]
+
+
 ALL_PINS = [v for k, v in dict(globals()).items() if k.startswith("pin_")]

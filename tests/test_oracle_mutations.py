@@ -141,6 +141,61 @@ def _mut_c_without_max(mp):
                 "c = lmax * math.sqrt(psi / lmin)")
 
 
+def _mut_c_estimates_swapped(mp):
+    _mut_source(mp, "c = max(1.0, lmax * math.sqrt(psi / lmin))",
+                "c = max(1.0, lmin * math.sqrt(psi / lmax))")
+
+
+def _mut_kappa_without_sqrt(mp):
+    _mut_source(mp, "    return math.sqrt(hi / lo)", "    return hi / lo")
+
+
+def _mut_absolute_residual_in_condy(mp):
+    _mut_source(mp, "rho_m = math.sqrt(max(G[r_idx, r_idx], 0.0)) / nb",
+                "rho_m = math.sqrt(max(G[r_idx, r_idx], 0.0))")
+
+
+def _mut_absolute_phi(mp):
+    _mut_source(mp, "phi = math.sqrt(rGr) / nb", "phi = math.sqrt(rGr)")
+
+
+def _mut_ritz_start_at_one(mp):
+    _mut_source(mp, "            if i == 0:\n                mt_max = MaxRitzEstimate(zeta)",
+                "            if i <= 1:\n                mt_max = MaxRitzEstimate(zeta)")
+
+
+def _mut_no_basis_update(mp):
+    _mut_source(mp, "if improved and m > 1 and np.isfinite(lmax)",
+                "if False and m > 1 and np.isfinite(lmax)")
+
+
+def _mut_no_break(mp):
+    _mut_source(mp, "if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):   # (4.7)",
+                "if False:")
+
+
+def _mut_break_wrong_index(mp):
+    _mut_source(mp, "if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):   # (4.7)",
+                "if j < stilde - 1 and kappa[j + 1] >= tol / (c * u * phi):")
+
+
+def _mut_break_current_residual(mp):
+    _mut_source(mp, "if j < stilde - 1 and gam[j + 1] >= tol / (c * u * phi):   # (4.7)",
+                "if j < stilde - 1 and gam[j + 1] >= tol / (c * u * rho):")
+
+
+def _mut_eps_double(mp):
+    _mut_source(mp, "UNIT_ROUNDOFF = 2.0 ** -53", "UNIT_ROUNDOFF = 2.0 ** -52")
+
+
+def _mut_stilde_largest_passing(mp):
+    def f(kappa, thr):
+        ok = [l for l in range(1, len(kappa) + 1) if kappa[l - 1] <= thr]
+        return max(ok) if ok else 1
+    mp.setattr(OS, "select_stilde", f)
+    mp.setattr(O, "select_stilde", f)
+
+
 MUTATIONS = {
     "alg3_wrong_zeta": _mut_alg3_wrong_zeta,
     "alg4_coupling_sign": _mut_alg4_sign,
@@ -156,17 +211,27 @@ MUTATIONS = {
     "alpha_without_B": _mut_alpha_without_B,
     "hscg_beta_scaled": _mut_hscg_beta,
     "c_without_max": _mut_c_without_max,
+    "c_estimates_swapped": _mut_c_estimates_swapped,
+    "kappa_without_sqrt": _mut_kappa_without_sqrt,
+    "absolute_residual_in_condy": _mut_absolute_residual_in_condy,
+    "absolute_phi_in_break": _mut_absolute_phi,
+    "ritz_start_at_one": _mut_ritz_start_at_one,
+    "no_basis_update": _mut_no_basis_update,
+    "no_break": _mut_no_break,
+    "break_index_kappa_j1": _mut_break_wrong_index,
+    "stilde_largest_passing": _mut_stilde_largest_passing,
+    "break_current_residual": _mut_break_current_residual,
+    "eps_2_pow_52": _mut_eps_double,
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(name, monkeypatch):
     MUTATIONS[name](monkeypatch)
-    failed = []
     for pin in pins.ALL_PINS:
         try:
             pin()
         except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError, KeyError,
                 IndexError, np.linalg.LinAlgError):
-            failed.append(pin.__name__)
-    assert failed, f"no pin caught mutation {name}"
+            return                                  # caught by this pin
+    pytest.fail(f"no pin caught mutation {name}")
