@@ -252,6 +252,25 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
                          const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
                          assg_info_t* info);
 
+/* assg_solve with the s-step schedule of its first loops given, for tests
+ * that separate arithmetic from decisions.  Algorithm 5 compares
+ * kappa(Y_{k,l}) and the residuals against thresholds ((3.2), (4.7), the
+ * stopping test), so two correct implementations whose roundings differ can
+ * take different s_k near a threshold and follow different trajectories;
+ * replaying one schedule removes that freedom.  Loop k < nsk runs exactly
+ * sk[k] inner steps (sk: host array of nsk >= 1 entries, 1 <= sk[k] <=
+ * s-bar_k with s-bar_0 = s_init and s-bar_k = min(sk[k-1] + growth, s_max),
+ * else ASSG_ERR_INVALID_ARG): the selection (3.2), the break (4.7) and the
+ * in-loop stopping test are not applied there (kappa is still computed and
+ * traced).  Loop nsk - 1 ends with the true-residual check; if it does not
+ * confirm convergence the solve goes on as assg_solve would (opts.max_outer
+ * and max_iters still apply).  Everything else, kernels included, is
+ * assg_solve's; the handle keeps a device copy of the schedule. */
+assg_status_t assg_solve_forced_schedule(assg_handle_t h, const assg_csr_t* A, const double* b,
+                                         double* x, const assg_opts_t* opts, const int32_t* sk,
+                                         int64_t nsk, void* workspace, size_t workspace_bytes,
+                                         assg_info_t* info);
+
 /* Algorithm 1 (HSCG) on the GPU: one SpMV with a fused p^T A p partial sum,
  * one update kernel with a fused r^T r partial sum and one direction update
  * per iteration; stopping as for assg_solve (updated residual <= tol, then

@@ -87,7 +87,7 @@ EXPORTS = [
     "assg_default_opts", "assg_status_string", "assg_last_error", "assg_struct_sizes",
     "assg_create", "assg_destroy", "assg_set_stream", "assg_basis_params",
     "assg_workspace_size", "assg_analyze", "assg_solve", "assg_hscg_solve", "assg_get_trace",
-    "assg_spmv", "assg_basis_gram", "assg_block_controller",
+    "assg_spmv", "assg_basis_gram", "assg_block_controller", "assg_solve_forced_schedule",
 ]
 
 _lib = None
@@ -116,6 +116,9 @@ def lib():
         "assg_analyze": (I32, [P, C.POINTER(AssgCsr)]),
         "assg_solve": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts), P, C.c_size_t,
                              C.POINTER(AssgInfo)]),
+        "assg_solve_forced_schedule": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts),
+                                             C.POINTER(I32), I64, P, C.c_size_t,
+                                             C.POINTER(AssgInfo)]),
         "assg_hscg_solve": (I32, [P, C.POINTER(AssgCsr), P, P, D, I64, P, C.c_size_t,
                                   C.POINTER(AssgInfo)]),
         "assg_get_trace": (I32, [P, C.POINTER(AssgTrace), I64, C.POINTER(C.c_int64)]),
@@ -299,6 +302,21 @@ def assg_solve(h: Handle, A: DeviceCSR, b, x, opts: AssgOpts | None = None, work
     _check(lib().assg_solve(h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"),
                             C.byref(opts), ws, wsb,
                             C.byref(info)), h.ptr)
+    return _info_dict(info)
+
+
+def assg_solve_forced_schedule(h: Handle, A: DeviceCSR, b, x, sk, opts: AssgOpts | None = None,
+                               workspace=None) -> dict:
+    """assg_solve with loop k running exactly sk[k] inner steps (a schedule
+    taken from another run, e.g. the oracle's trace)."""
+    opts = opts or assg_default_opts()
+    sk = np.ascontiguousarray(sk, dtype=np.int32)
+    info = AssgInfo()
+    d = A.c()
+    ws, wsb = (None, 0) if workspace is None else (_dptr(workspace), workspace.numel() * workspace.element_size())
+    _check(lib().assg_solve_forced_schedule(
+        h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"), C.byref(opts),
+        sk.ctypes.data_as(C.POINTER(C.c_int32)), int(sk.size), ws, wsb, C.byref(info)), h.ptr)
     return _info_dict(info)
 
 

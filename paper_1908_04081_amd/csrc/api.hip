@@ -346,8 +346,9 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_blke) (void)hipFree(h->d_blke);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_part) (void)hipFree(h->d_part);
-  if (h->g_sstep.exec) (void)hipGraphExecDestroy(h->g_sstep.exec);
-  if (h->g_hscg.exec) (void)hipGraphExecDestroy(h->g_hscg.exec);
+  drop_graph(h->g_sstep);
+  drop_graph(h->g_hscg);
+  if (h->d_forced) (void)hipFree(h->d_forced);
   batch_release(h);
   if (h->d_ctl) (void)hipFree(h->d_ctl);
   if (h->d_flag) (void)hipFree(h->d_flag);
@@ -370,6 +371,10 @@ assg_status_t assg_set_stream(assg_handle_t h, void* stream) {
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   if (!h) return ASSG_ERR_INVALID_ARG;
   h->an_n = -1;   // no solve runs on an earlier analysis once a new one is asked for
+  // the cached graphs were captured with the old partition tables and sizes
+  if (h->stream) HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  drop_graph(h->g_sstep);
+  drop_graph(h->g_hscg);
   if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
   std::vector<int32_t> rp((size_t)A->n + 1);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
@@ -453,9 +458,11 @@ assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, co
 }
 
 
-assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
-                         const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
-                         assg_info_t* info) {
+// assg_solve, and with ``forced`` (host, nsk entries) its schedule-replay
+// form assg_solve_forced_schedule.
+static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                                const assg_opts_t* opts, const int32_t* forced, int64_t nsk,
+                                void* workspace, size_t workspace_bytes, assg_info_t* info) {
   if (!h) return ASSG_ERR_INVALID_ARG;
   if (!b || !x || !info) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = validate_opts(h, opts);
@@ -463,9 +470,29 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
   if (overlap(b, x, A->n)) return fail(h, ASSG_ERR_INVALID_ARG, "b and x overlap");
+  const int sigma = opts->s_max;
+  if (forced) {
+    // every s_k must fit the s-bar its predecessor implies
+    const int growth = opts->growth > 0 ? opts->growth : sigma;
+    int sbar = opts->s_init > 0 ? opts->s_init : sigma;
+    if (nsk < 1 || nsk > (1 << 20)) return fail(h, ASSG_ERR_INVALID_ARG, "schedule length out of range");
+    for (int64_t k = 0; k < nsk; ++k) {
+      if (forced[k] < 1 || forced[k] > sbar)
+        return fail(h, ASSG_ERR_INVALID_ARG, "schedule entry " + std::to_string(k) +
+                                                 " outside 1..s-bar of its loop");
+      sbar = std::min(forced[k] + growth, sigma);
+    }
+    if (h->forced_cap < nsk) {
+      if (h->d_forced) HIP_OR_FAIL(h, hipFree(h->d_forced));
+      h->d_forced = nullptr;
+      h->forced_cap = 0;
+      if (hipMalloc(&h->d_forced, nsk * sizeof(int32_t)) != hipSuccess)
+        return fail(h, ASSG_ERR_ALLOC, "schedule allocation failed");
+      h->forced_cap = nsk;
+    }
+  }
   std::memset(info, 0, sizeof(*info));
   const int64_t n = A->n;
-  const int sigma = opts->s_max;
   char* base = nullptr;
   WsLayout lay;
   st = get_workspace(h, n, sigma, workspace, workspace_bytes, &base, &lay);
@@ -500,10 +527,15 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   c->max_outer = max_outer;
   c->max_iters = max_iters;
   c->tol = opts->tol;
+  c->forced_sk = forced ? h->d_forced : nullptr;
+  c->forced_len = forced ? nsk : 0;
   apply_variant(c, opts);
 
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
+  if (forced)
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_forced, forced, nsk * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
   launch_setup(h->stream, h->d_ctl, Av, b, x, pairs, h->d_part);
@@ -523,9 +555,12 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
     // outer loops replayed from a captured graph of LOOPS_PER_GRAPH loops
     constexpr int LOOPS_PER_GRAPH = 4;
     const std::vector<const void*> key{A->row_ptr, A->col_idx, A->val, b, x, base, h->d_trace,
-                                       h->d_blk, h->d_chunks, h->d_part,
+                                       h->d_blk, h->d_blke, h->d_chunks, h->d_part,
                                        reinterpret_cast<const void*>((intptr_t)sigma),
-                                       reinterpret_cast<const void*>((intptr_t)n)};
+                                       reinterpret_cast<const void*>((intptr_t)n),
+                                       reinterpret_cast<const void*>((intptr_t)A->nnz),
+                                       reinterpret_cast<const void*>((intptr_t)h->nblk),
+                                       reinterpret_cast<const void*>((intptr_t)h->nchunk)};
     st = cached_graph(h, h->g_sstep, key, [&]() {
       for (int r = 0; r < LOOPS_PER_GRAPH; ++r) {
         for (int l = 1; l < sigma; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
@@ -622,6 +657,21 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
   return ASSG_OK;
 }
 
+assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                         const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
+                         assg_info_t* info) {
+  return solve_impl(h, A, b, x, opts, nullptr, 0, workspace, workspace_bytes, info);
+}
+
+assg_status_t assg_solve_forced_schedule(assg_handle_t h, const assg_csr_t* A, const double* b,
+                                         double* x, const assg_opts_t* opts, const int32_t* sk,
+                                         int64_t nsk, void* workspace, size_t workspace_bytes,
+                                         assg_info_t* info) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!sk) return fail(h, ASSG_ERR_INVALID_ARG, "null schedule");
+  return solve_impl(h, A, b, x, opts, sk, nsk, workspace, workspace_bytes, info);
+}
+
 assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t cap,
                              int64_t* count) {
   if (!h || !count || (cap > 0 && !host_buf)) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
@@ -670,8 +720,11 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   // iterations replayed from a captured graph of ITERS_PER_GRAPH iterations
   constexpr int ITERS_PER_GRAPH = 16;
   const std::vector<const void*> key{A->row_ptr, A->col_idx, A->val, b, x, base, h->d_blk,
-                                     h->d_chunks, h->d_part,
-                                     reinterpret_cast<const void*>((intptr_t)n)};
+                                     h->d_blke, h->d_chunks, h->d_part,
+                                     reinterpret_cast<const void*>((intptr_t)n),
+                                     reinterpret_cast<const void*>((intptr_t)A->nnz),
+                                     reinterpret_cast<const void*>((intptr_t)h->nblk),
+                                     reinterpret_cast<const void*>((intptr_t)h->nchunk)};
   st = cached_graph(h, h->g_hscg, key, [&]() {
     for (int it = 0; it < ITERS_PER_GRAPH; ++it) {
       launch_h_spmv(h->stream, h->d_ctl, Av, p, w, h->d_part);

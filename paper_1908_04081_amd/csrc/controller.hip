@@ -249,6 +249,14 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       break;
   }
   if (variant == ASSG_FIXED_SSTEP) st = sbar;   // fixed s-step CG: the whole basis
+  // a given schedule replaces (3.2), the break and the in-loop stopping test
+  // in its loops; the loops after it decide for themselves
+  const bool forced = ctl->forced_sk && (int64_t)ctl->k < ctl->forced_len;
+  const bool last_forced = forced && (int64_t)ctl->k + 1 == ctl->forced_len;
+  if (forced) {
+    const int32_t f = ctl->forced_sk[ctl->k];
+    st = f < 1 ? 1 : (f > sbar ? sbar : f);
+  }
   const int n = 2 * st + 1;
 
   // ---- inner loop (interleaved coordinates; lane i owns coordinate i and
@@ -329,6 +337,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       ctl->betas[j] = beta;
     }
     if (!isfinite(alpha) || !isfinite(beta)) { outcome = ASSG_DIVERGED; break; }
+    if (forced) continue;
     if (rho <= tol) { candidate = 1; break; }
     if (variant <= ASSG_IMPROVED_C_ONE) {
       if (j < st - 1 && sKappa[j + 2] >= tol / (c * u * phi)) break;   // (4.7), gamma_{j+1}
@@ -337,6 +346,9 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       if (j < st - 1 && sKappa[st] >= tol / (c * u * rho)) break;
     }
   }
+
+  // the last loop of a given schedule ends with the true-residual check
+  if (last_forced && outcome == ST_RUNNING) candidate = 1;
 
   // ---- results
   if (lane < MAXC) {

@@ -39,6 +39,8 @@ struct alignas(256) Ctl {
   // -------------------------------------------------------------- options
   int32_t sigma, growth, basis, record_trace;
   int64_t trace_cap, max_outer, max_iters;
+  const int32_t* forced_sk;   // test hook: s_k of every loop given (device), else null
+  int64_t forced_len;
   double tol;
   double c_const;        // c of the old adaptive method
 

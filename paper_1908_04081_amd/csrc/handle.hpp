@@ -25,6 +25,8 @@ struct assg_handle_s {
   assg_trace_t* d_trace = nullptr;
   int64_t trace_cap = 0;
   int64_t trace_count = 0;
+  int32_t* d_forced = nullptr;   // schedule of assg_solve_forced_schedule
+  int64_t forced_cap = 0;
   void* ws = nullptr;            // owned workspace
   size_t ws_bytes = 0;
   // analysis
@@ -109,6 +111,14 @@ void batch_release(assg_handle_t h);
 
 // The graph of ``enqueue``'s launches on the handle's stream for ``key``:
 // captured and instantiated when the key differs from the cached one.
+// Forgets a cached graph (its kernels hold the partition tables and sizes of
+// the analysis they were captured under).
+inline void drop_graph(assg_handle_s::GraphCache& gc) {
+  if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  gc.exec = nullptr;
+  gc.key.clear();
+}
+
 template <class F>
 assg_status_t cached_graph(assg_handle_t h, assg_handle_s::GraphCache& gc,
                            const std::vector<const void*>& key, F enqueue) {

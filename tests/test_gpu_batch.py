@@ -8,7 +8,7 @@ import scipy.sparse as sp
 
 import oracle as O
 import spd_problems as P
-from gpu_util import oracle_outer_spread, torch_cuda
+from gpu_util import check_outer_parity, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -57,11 +57,11 @@ def test_batch_matches_oracle_per_system(env, basis, sigma):
         rel = np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b)
         assert rel <= tol, (pr.name, rel)
         assert abs(ig["relres_true"] - rel) <= 1e-3 * rel
-        if abs(ig["outer_iters"] - io["outer"]) > 1:
-            lo, hi = oracle_outer_spread(pr, s_max=sigma, tol=tol, basis=basis)
-            assert lo - 1 <= ig["outer_iters"] <= hi + 1, (pr.name, ig["outer_iters"], lo, hi)
         err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
         assert err <= 1e-8, (pr.name, err)
+        check_outer_parity(torch, L, h, pr, ig, xo, io,
+                           dict(s_max=sigma, s_init=sigma, growth=sigma, tol=tol, basis=basis),
+                           case=f"batch {pr.name} {basis} sigma={sigma}")
 
 
 def test_batch_zero_rhs_and_breakdown_are_per_system(env):
@@ -125,10 +125,10 @@ def test_batched_workload_full_size(env):
     for i in order:
         pr = probs[i]
         xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=10, tol=1e-10, basis="chebyshev")
-        if abs(infos[i]["outer_iters"] - io["outer"]) > 1:
-            lo, hi = oracle_outer_spread(pr, s_max=10, tol=1e-10, basis="chebyshev")
-            assert lo - 1 <= infos[i]["outer_iters"] <= hi + 1, (pr.name, lo, hi)
         assert np.linalg.norm(xs[i] - xo) / np.linalg.norm(xo) <= 1e-8
+        check_outer_parity(torch, L, h, pr, infos[i], xo, io,
+                           dict(s_max=10, tol=1e-10, basis="chebyshev"),
+                           case=f"batched workload {pr.name}")
 
 
 def test_batch_at_maximum_size(env):
