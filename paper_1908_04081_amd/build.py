@@ -29,7 +29,8 @@ COMMON = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith(".hip") or f.endswith(".cpp"))
 
 
 def _compile(src, extra):
@@ -57,8 +58,26 @@ def build(verbose: bool = False, extra=()) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe()
     build_example()
     return LIB
+
+
+PROBE_DIR = os.path.join(PKG, "bwprobe")
+PROBE_LIB = os.path.join(PROBE_DIR, "libassg_bwprobe.so")
+
+
+def build_probe() -> str:
+    """The bandwidth probes (paper_1908_04081_amd/bwprobe), a library of their
+    own: measurement kernels, not part of the solver's ABI."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, f"-I{PROBE_DIR}", "-shared", "-o", tmp,
+           os.path.join(PROBE_DIR, "bwprobe.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the bandwidth probes:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 EXAMPLE_SRC = os.path.join(PKG, "examples", "poisson2d.c")

@@ -6,11 +6,11 @@
 #include <stdint.h>
 
 #include "ctl.hpp"
+#include "partition.hpp"
 
 namespace assg {
 
 constexpr int WAVE = 64;
-constexpr int NXCD = 8;          // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 // ---------------------------------------------------------------- loads
 // Streaming (non-temporal) accesses for data read or written once per

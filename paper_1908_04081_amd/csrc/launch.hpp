@@ -8,13 +8,9 @@
 
 #include "assg.h"
 #include "ctl.hpp"
+#include "partition.hpp"
 
 namespace assg {
-
-// Row blocks of the CSR-stream kernels: at most SB_ROWS rows and SB_CAP
-// nonzeros each, except single rows longer than SB_CAP.
-constexpr int SB_ROWS = 256;
-constexpr int SB_CAP = 2048;
 
 // A matrix with its row-block partition.  A batch of independent systems
 // is one block-diagonal matrix (systems' rows and columns concatenated);
@@ -37,23 +33,8 @@ struct CsrView {
   int32_t nsys;
 };
 
-// Greedy row-block partition (host): rows are appended while a block has
-// fewer than ``rows`` rows and at most ``cap`` (<= SB_CAP) nonzeros.
-void make_blocks(const int32_t* row_ptr, int64_t n, std::vector<int32_t>& blk,
-                 int rows = SB_ROWS, int cap = SB_CAP);
-
-// Chunks over the row blocks of each system (sys_blk: nsys + 1 block
-// starts): about ``target`` chunks in all, in proportion to each system's
-// blocks, at least one per system, padded with empty chunks to a multiple
-// of 8.
-void make_chunks(const std::vector<int32_t>& sys_blk, int target, std::vector<int32_t>& cblk,
-                 std::vector<int32_t>& csys, std::vector<int32_t>& sys_chunk);
-
 void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
 
-// Per-workgroup partial sums of the grid reductions over the row-block grid
-// (two sums for the HSCG start).
-size_t reduce_doubles(int32_t nblk);
 
 // Kernels of the s-step path take the control blocks of all systems
 // (ctl[i] for system i) and run every system of the batch.
