@@ -69,10 +69,37 @@ def mpk_bytes(n: int, nnz: int, s: int, chebyshev: bool):
     return total, sweep_ge2, sweep1, last
 
 
+def time_solves(run, warmup, steps, torch):
+    """``warmup`` untimed calls of ``run()``, then ``steps`` timed ones, the
+    device synchronized before and after each; returns the per-call wall
+    times and the last call's result."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    times, res = [], None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    return times, res
+
+
+def summary(times, info, extra=None):
+    d = {"s_median": round(float(np.median(times)), 5), "s_min": round(min(times), 5),
+         "s_mean": round(float(np.mean(times)), 5), "runs": len(times),
+         "outer_iters": info["outer_iters"], "total_iters": info["total_iters"],
+         "outcome": info["outcome_name"], "relres_true": info["relres_true"]}
+    if extra:
+        d.update(extra)
+    return d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
@@ -83,8 +110,9 @@ def main():
                     help="skip the table of the paper's comparison methods")
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the 160^3 27-point diffusion workload")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 64x64 Poisson workload (GPU and oracle times)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the bandwidth probes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU (its path on one GPU's share of the "
@@ -98,6 +126,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ceilings = None if args.no_probe else bandwidth_ceilings(torch, dev)
     t0 = time.perf_counter()
     pr = P.make_config("poisson3d_256", size=args.size)
     n, nnz = pr.n, pr.A.nnz
@@ -111,86 +140,82 @@ def main():
     sigma, tol = 10, 1e-10
     max_iters = 200000
 
-    def solve(basis, timing):
+    def solve(basis, timing=False):
         x.zero_()
         opts = L.assg_default_opts(s_max=sigma, s_init=sigma, growth=sigma, tol=tol, basis=basis,
                                    max_iters=max_iters, time_kernels=1 if timing else 0)
         return L.assg_solve(h, A, b, x, opts)
 
-    # ---- adaptive s-step CG, Chebyshev basis: the timed steps
+    def hscg():
+        x.zero_()
+        return L.assg_hscg_solve(h, A, b, x, tol, max_iters)
+
+    # ---- the headline: adaptive s-step CG, Chebyshev basis, production path
+    # (outer loops replayed from the captured graph); exactly --steps timed
+    # solves between two device synchronizations
     for _ in range(args.warmup):
-        solve("chebyshev", True)
+        solve("chebyshev")
     torch.cuda.synchronize()
-    infos = []
+    per, last = [], None
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(solve("chebyshev", True))
+        last = solve("chebyshev")
+        per.append(last["solve_ms"] * 1e-3)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_step = 1e3 * t_total / args.steps
-    last = infos[-1]
     xg = x.cpu().numpy()
     relres = float(np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b))
     print(f"[bench] chebyshev: {ms_step:.1f} ms/solve outer={last['outer_iters']} "
           f"iters={last['total_iters']} relres(host)={relres:.3e} {last['outcome_name']}",
           file=sys.stderr, flush=True)
 
-    sweep_ms = sum(i["sweep_ms"] for i in infos)
-    sweep_n = sum(i["sweep_launches"] for i in infos)
-    sweep1_ms = sum(i["sweep1_ms"] for i in infos)
-    sweep1_n = sum(i["sweep1_launches"] for i in infos)
-    lastg_ms = sum(i["last_gram_ms"] for i in infos)
-    lastg_n = sum(i["last_gram_launches"] for i in infos)
-    tot_b, sweep_b, sweep1_b, last_b = mpk_bytes(n, nnz, sigma, True)
-    sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    achieved = sweep_b / (sweep_avg_ms * 1e-3) / 1e9
-    mpk_time_ms = (sweep_ms + sweep1_ms + lastg_ms) / max(lastg_n, 1)     # per outer loop
-    mpk_gbps = tot_b / (mpk_time_ms * 1e-3) / 1e9
-
     extra = {}
+    methods = {"chebyshev": {"s_median_device": round(float(np.median(per)), 5),
+                             "s_min_device": round(min(per), 5), "s_mean_wall": round(ms_step * 1e-3, 5),
+                             "runs": args.steps, "outer_iters": last["outer_iters"],
+                             "total_iters": last["total_iters"], "outcome": last["outcome_name"],
+                             "relres_true": last["relres_true"]}}
     if not args.no_compare:
-        # ---- Newton basis
-        solve("newton", True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        inf_n = solve("newton", True)
-        torch.cuda.synchronize()
-        t_newton = time.perf_counter() - t1
-        tot_nb, sweep_nb, _, _ = mpk_bytes(n, nnz, sigma, False)
-        extra["newton"] = {
-            "s": round(t_newton, 4), "outer_iters": inf_n["outer_iters"],
-            "total_iters": inf_n["total_iters"], "outcome": inf_n["outcome_name"],
-            "sweep_avg_ms": round(inf_n["sweep_ms"] / max(inf_n["sweep_launches"], 1), 4),
-            "sweep_GBps": round(sweep_nb / (inf_n["sweep_ms"] / max(inf_n["sweep_launches"], 1)
-                                           * 1e-3) / 1e9, 1),
-        }
-        # ---- plain HSCG on the same GPU
-        x.zero_()
-        L.assg_hscg_solve(h, A, b, x, tol, max_iters)
-        torch.cuda.synchronize()
-        x.zero_()
-        t1 = time.perf_counter()
-        inf_h = L.assg_hscg_solve(h, A, b, x, tol, max_iters)
-        torch.cuda.synchronize()
-        t_hscg = time.perf_counter() - t1
-        extra["hscg"] = {"s": round(t_hscg, 4), "iters": inf_h["total_iters"],
-                         "outcome": inf_h["outcome_name"],
-                         "relres_true": inf_h["relres_true"]}
-        extra["speedup_vs_hscg"] = round(t_hscg / (ms_step * 1e-3), 3)
-        print(f"[bench] newton {t_newton*1e3:.1f} ms outer={inf_n['outer_iters']}; "
-              f"hscg {t_hscg*1e3:.1f} ms iters={inf_h['total_iters']}", file=sys.stderr, flush=True)
+        # Newton basis and plain HSCG, the same protocol (warm-up, then timed
+        # solves on the production path; median and min)
+        tn, inf_n = time_solves(lambda: solve("newton"), args.warmup, args.steps, torch)
+        th, inf_h = time_solves(hscg, args.warmup, args.steps, torch)
+        tc, inf_c = time_solves(lambda: solve("chebyshev"), 0, args.steps, torch)
+        methods["chebyshev_wall"] = summary(tc, inf_c)
+        methods["newton"] = summary(tn, inf_n)
+        methods["hscg"] = summary(th, inf_h)
+        extra["speedup_vs_hscg"] = {
+            "chebyshev": round(float(np.median(th)) / float(np.median(tc)), 3),
+            "newton": round(float(np.median(th)) / float(np.median(tn)), 3),
+            "basis": "median wall time of --steps solves each, same warm-up"}
+        print(f"[bench] median wall: chebyshev {np.median(tc)*1e3:.1f} ms, newton "
+              f"{np.median(tn)*1e3:.1f} ms, hscg {np.median(th)*1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    extra["methods"] = methods
 
-    if args.copy_calib:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # ---- per-kernel times: a separate solve with HIP events around every
+    # matrix-powers launch on the library's stream (same kernels, launched
+    # one by one instead of from the graph; bit-identical iterates)
+    kt = solve("chebyshev", timing=True)
+    tot_b, sweep_b, sweep1_b, last_b = mpk_bytes(n, nnz, sigma, True)
+    sweep_avg_ms = kt["sweep_ms"] / max(kt["sweep_launches"], 1)
+    achieved = sweep_b / (sweep_avg_ms * 1e-3) / 1e9
+    lastg_avg_ms = kt["last_gram_ms"] / max(kt["last_gram_launches"], 1)
+    mpk_time_ms = (kt["sweep_ms"] + kt["sweep1_ms"] + kt["last_gram_ms"]) / \
+        max(kt["last_gram_launches"], 1)      # per outer loop
+    mpk_gbps = tot_b / (mpk_time_ms * 1e-3) / 1e9
+    if not args.no_compare:
+        kn = solve("newton", timing=True)
+        _, sweep_nb, _, _ = mpk_bytes(n, nnz, sigma, False)
+        nav = kn["sweep_ms"] / max(kn["sweep_launches"], 1)
+        methods["newton"]["sweep_avg_ms"] = round(nav, 4)
+        methods["newton"]["sweep_GBps"] = round(sweep_nb / (nav * 1e-3) / 1e9, 1)
 
+    if not args.no_small:
+        extra["poisson2d_64"] = bench_small(L, P, torch, args.warmup, args.steps)
     if not args.no_diffusion:
-        extra["diffusion27_160"] = bench_diffusion(L, P, torch)
+        extra["diffusion27_160"] = bench_diffusion(L, P, torch, args.warmup, args.steps)
     if not args.no_variants:
         extra["variants"] = bench_variants(L, P, torch)
     if not args.no_batch:
@@ -231,15 +256,19 @@ def main():
             "traffic": measured_traffic() if args.size == 256 else None,
             "bytes_per_launch": sweep_b,
             "avg_launch_ms": round(sweep_avg_ms, 5),
-            "launches": sweep_n,
+            "launches": kt["sweep_launches"],
+            "timing": "HIP events on the library's stream around each launch, in a separate "
+                      "solve of the same workload with time_kernels=1",
         },
         "mpk_gram": {
             "GBps": round(mpk_gbps, 1), "frac": round(mpk_gbps / PEAK_HBM_GBPS, 4),
             "bytes_per_outer_loop": tot_b, "ms_per_outer_loop": round(mpk_time_ms, 4),
-            "last_gram_avg_ms": round(lastg_ms / max(lastg_n, 1), 4),
-            "last_gram_GBps": round(last_b / (lastg_ms / max(lastg_n, 1) * 1e-3) / 1e9, 1),
-            "sweep1_avg_ms": round(sweep1_ms / max(sweep1_n, 1), 4),
+            "last_gram_avg_ms": round(lastg_avg_ms, 4),
+            "last_gram_GBps": round(last_b / (lastg_avg_ms * 1e-3) / 1e9, 1),
+            "last_gram_frac": round(last_b / (lastg_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+            "sweep1_avg_ms": round(kt["sweep1_ms"] / max(kt["sweep1_launches"], 1), 4),
         },
+        "ceilings": ceilings,
         "solve": {"outer_iters": last["outer_iters"], "total_iters": last["total_iters"],
                   "relres_true": relres, "outcome": last["outcome_name"],
                   "device_solve_ms": round(last["solve_ms"], 3)},
@@ -248,6 +277,76 @@ def main():
     out.update(extra)
     print(json.dumps(out))
     L.assg_destroy(h)
+
+
+def bandwidth_ceilings(torch, dev):
+    """Measured ceilings of this GPU (project-written probe kernels, HIP
+    events): a streaming read and a streaming copy of 1 GiB, and repeated
+    ordinary reads of a 128 MiB buffer (served by the 256 MB Infinity Cache
+    after the first pass)."""
+    from paper_1908_04081_amd import bwprobe
+    big = torch.ones(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
+    dst = torch.empty_like(big)
+    read_nt, ms_r = bwprobe.read_gbps(big, nontemporal=True)
+    read_t, _ = bwprobe.read_gbps(big, nontemporal=False)
+    copy, ms_c = bwprobe.copy_gbps(big, dst)
+    del dst
+    small = big[: 1 << 24]                                              # 128 MiB
+    mall, _ = bwprobe.read_gbps(small, nontemporal=False, iters=50)
+    del big, small
+    out = {"stream_read_1GiB_GBps": round(read_nt, 1), "read_1GiB_cached_loads_GBps": round(read_t, 1),
+           "stream_copy_1GiB_GBps": round(copy, 1), "reread_128MiB_GBps": round(mall, 1),
+           "peak_GBps": PEAK_HBM_GBPS,
+           "note": "paper_1908_04081_amd/bwprobe kernels; copy counts read + write bytes"}
+    print(f"[bench] ceilings: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_small(L, P, torch, warmup, steps):
+    """64 x 64 Poisson (N = 4,096), Chebyshev, sigma = 10, tol 1e-10: GPU
+    s-step and GPU HSCG (warm-up, then timed solves; median and min), and the
+    oracle's adaptive s-step CG and HSCG to the same tolerance on the host,
+    three times each."""
+    import oracle as O
+    pr = P.make_config("poisson2d_64")
+    A = L.csr_to_device(pr.A)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    h = L.assg_create()
+    L.assg_analyze(h, A)
+    opts = L.assg_default_opts(s_max=10, tol=1e-10, basis="chebyshev")
+
+    def ss():
+        x.zero_()
+        return L.assg_solve(h, A, b, x, opts)
+
+    def hs():
+        x.zero_()
+        return L.assg_hscg_solve(h, A, b, x, 1e-10, 0)
+
+    k = max(steps, 5)
+    ts, i_s = time_solves(ss, max(warmup, 1), k, torch)
+    th, i_h = time_solves(hs, max(warmup, 1), k, torch)
+    L.assg_destroy(h)
+    to, th_o = [], []
+    for _ in range(3):
+        t = time.perf_counter()
+        _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=10, tol=1e-10, basis="chebyshev",
+                                    record=False)
+        to.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        _, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
+        th_o.append(time.perf_counter() - t)
+    out = {"n": pr.n, "nnz": int(pr.A.nnz), "gpu_sstep": summary(ts, i_s), "gpu_hscg": summary(th, i_h),
+           "oracle_sstep": {"s_median": round(float(np.median(to)), 4), "s_min": round(min(to), 4),
+                            "runs": 3, "outer_iters": io["outer"], "total_iters": io["iters"]},
+           "oracle_hscg": {"s_median": round(float(np.median(th_o)), 4), "s_min": round(min(th_o), 4),
+                           "runs": 3, "iters": ih["iters"]},
+           "speedup_vs_gpu_hscg": round(float(np.median(th)) / float(np.median(ts)), 3)}
+    print(f"[bench] poisson2d_64: gpu s-step {np.median(ts)*1e3:.2f} ms, gpu hscg "
+          f"{np.median(th)*1e3:.2f} ms, oracle s-step {np.median(to)*1e3:.0f} ms",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def bench_variants(L, P, torch):
@@ -303,9 +402,10 @@ def bench_variants(L, P, torch):
     return tables
 
 
-def bench_diffusion(L, P, torch):
+def bench_diffusion(L, P, torch, warmup, steps):
     """27-point lognormal (sigma = 2) diffusion on 160^3, Jacobi-scaled, b ~
-    N(0, 1), sigma = 10, tol 1e-10: both bases and HSCG, best of two each."""
+    N(0, 1), sigma = 10, tol 1e-10: both bases and HSCG, each warm-up then
+    --steps timed solves (median and min)."""
     pr = P.make_config("diffusion27_160")
     A = L.csr_to_device(pr.A)
     b = torch.from_numpy(pr.b).cuda()
@@ -314,25 +414,17 @@ def bench_diffusion(L, P, torch):
     L.assg_analyze(h, A)
     out = {"n": pr.n, "nnz": int(pr.A.nnz)}
     for basis in ("chebyshev", "newton", "hscg"):
-        best, inf = 1e9, None
-        for _ in range(2):
+        def run(basis=basis):
             x.zero_()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
             if basis == "hscg":
-                inf = L.assg_hscg_solve(h, A, b, x, 1e-10, 0)
-            else:
-                inf = L.assg_solve(h, A, b, x, L.assg_default_opts(s_max=10, tol=1e-10,
-                                                                   basis=basis))
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t)
-        out[basis] = {"s": round(best, 4), "outer_iters": inf["outer_iters"],
-                      "total_iters": inf["total_iters"], "outcome": inf["outcome_name"],
-                      "relres_true": inf["relres_true"]}
-    out["speedup_vs_hscg"] = round(out["hscg"]["s"] / out["chebyshev"]["s"], 3)
+                return L.assg_hscg_solve(h, A, b, x, 1e-10, 0)
+            return L.assg_solve(h, A, b, x, L.assg_default_opts(s_max=10, tol=1e-10, basis=basis))
+        t, inf = time_solves(run, warmup, steps, torch)
+        out[basis] = summary(t, inf)
+    out["speedup_vs_hscg"] = round(out["hscg"]["s_median"] / out["chebyshev"]["s_median"], 3)
     L.assg_destroy(h)
-    print(f"[bench] diffusion27_160: chebyshev {out['chebyshev']['s']*1e3:.1f} ms, newton "
-          f"{out['newton']['s']*1e3:.1f} ms, hscg {out['hscg']['s']*1e3:.1f} ms",
+    print(f"[bench] diffusion27_160: chebyshev {out['chebyshev']['s_median']*1e3:.1f} ms, newton "
+          f"{out['newton']['s_median']*1e3:.1f} ms, hscg {out['hscg']['s_median']*1e3:.1f} ms",
           file=sys.stderr, flush=True)
     return out
 
