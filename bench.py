@@ -498,7 +498,14 @@ def bench_batch(L, P, torch):
 
 def bench_grad(L, P, torch):
     """Differentiable workload: varcoef7 128^3, L = ||x - t||^2, gradients in b
-    and in A's values from the forward and adjoint solves at tol 1e-12."""
+    and in A's values from the forward and adjoint solves at tol 1e-12, with
+    the basis growth factor f = sigma (Section 5's choice) and f = 2 (fewer
+    levels built when (3.2) keeps s~ small, which it does for the adjoint
+    right-hand side: its residual norm climbs above ||b|| early on).  Also
+    the relative residual plain HSCG attains on the adjoint right-hand side
+    at tol 1e-12, and the adjoint's outer loops with s~ = 1."""
+    import warnings
+
     from paper_1908_04081_amd import autograd as AG
     pr = P.make_config("varcoef7_128")
     n = pr.n
@@ -508,30 +515,47 @@ def bench_grad(L, P, torch):
     t = torch.from_numpy(P.rhs_normal(n, 2105)).cuda()
     b0 = torch.from_numpy(pr.b).cuda()
 
-    def run():
+    def run(growth):
         val = pat.val.clone().requires_grad_(True)
         b = b0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x = AG.solve(pat, val, b, handle=h, tol=1e-12, s_max=10, basis="chebyshev")
+        x = AG.solve(pat, val, b, handle=h, tol=1e-12, s_max=10, basis="chebyshev",
+                     growth=growth, record_trace=1)
         loss = ((x - t) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        loss.backward()
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", AG.SolveStagnated)
+            loss.backward()
         torch.cuda.synchronize()
-        return t1 - t0, time.perf_counter() - t1
+        return t1 - t0, time.perf_counter() - t1, x.detach()
 
-    run()
-    fwd, bwd = run()
-    fi, ai = AG.last_info["forward"], AG.last_info["adjoint"]
-    L.assg_destroy(h)
-    print(f"[bench] differentiable: forward {fwd*1e3:.1f} ms, backward {bwd*1e3:.1f} ms",
-          file=sys.stderr, flush=True)
-    return {"workload": "varcoef7_128 (N=2,097,152), tol 1e-12", "forward_s": round(fwd, 4),
-            "backward_s": round(bwd, 4), "forward_outer": fi["outer_iters"],
+    out = {"workload": "varcoef7_128 (N=2,097,152), tol 1e-12, sigma = 10, Chebyshev"}
+    for growth in (10, 2):
+        run(growth)
+        fwd, bwd, x = run(growth)
+        fi, ai = AG.last_info["forward"], AG.last_info["adjoint"]
+        tr = L.assg_get_trace(h)                      # the adjoint solve's loops
+        out[f"f={growth}"] = {
+            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+            "backward_over_forward": round(bwd / fwd, 2),
+            "forward_outer": fi["outer_iters"], "forward_iters": fi["total_iters"],
             "forward_outcome": fi["outcome_name"], "forward_relres": fi["relres_true"],
-            "adjoint_outer": ai["outer_iters"], "adjoint_outcome": ai["outcome_name"],
-            "adjoint_relres": ai["relres_true"]}
+            "adjoint_outer": ai["outer_iters"], "adjoint_iters": ai["total_iters"],
+            "adjoint_outcome": ai["outcome_name"], "adjoint_relres": ai["relres_true"],
+            "adjoint_loops_stilde_1": sum(1 for r in tr if r["stilde"] == 1),
+            "adjoint_max_rho_m": max(r["rho_m"] for r in tr),
+            "adjoint_levels_built": sum(r["sbar"] for r in tr)}
+        print(f"[bench] differentiable f={growth}: forward {fwd*1e3:.1f} ms, backward "
+              f"{bwd*1e3:.1f} ms", file=sys.stderr, flush=True)
+    g = (2.0 * (x - t)).contiguous()
+    lam = torch.zeros_like(g)
+    hi = L.assg_hscg_solve(h, pat, g, lam, 1e-12, 0)
+    out["hscg_on_adjoint_rhs"] = {"outcome": hi["outcome_name"], "relres": hi["relres_true"],
+                                  "iters": hi["total_iters"]}
+    L.assg_destroy(h)
+    return out
 
 
 def cpu_baseline(pr, sigma, tol, gpu_outer):

@@ -10,14 +10,16 @@ directional derivative is the sum over both entries.
 
 A solve that ends STAGNATED (the true residual stopped improving above the
 tolerance: the attainable accuracy of the recurrence for that right-hand
-side, which plain CG shares) still returns its iterate; DIVERGED,
-BREAKDOWN and MAX_ITER raise.  The outcome and residuals of the last forward
+side, which plain CG shares) still returns its iterate and emits a
+SolveStagnated warning; DIVERGED, BREAKDOWN and MAX_ITER raise.  The outcome and residuals of the last forward
 and adjoint solves are kept in ``last_info``.
 
 PyTorch supplies the tensors and the autograd graph only; both solves and the
 gradient scatter run in the HIP library.
 """
 from __future__ import annotations
+
+import warnings
 
 import torch
 
@@ -31,10 +33,17 @@ class SolveError(RuntimeError):
     pass
 
 
-def _accept(info, what):
+class SolveStagnated(UserWarning):
+    """A forward or adjoint solve stopped above its tolerance (STAGNATED)."""
+
+
+def _accept(info, what, tol):
     last_info[what] = info
     if info["outcome"] not in (CONVERGED, STAGNATED):
         raise SolveError(f"{what} solve: {OUTCOME_NAMES.get(info['outcome'])}")
+    if info["outcome"] == STAGNATED:
+        warnings.warn(f"{what} solve stagnated at relative residual {info['relres_true']:.3e} "
+                      f"above tol {tol:.1e}; its iterate is used", SolveStagnated, stacklevel=3)
 
 
 class _Solve(torch.autograd.Function):
@@ -43,7 +52,7 @@ class _Solve(torch.autograd.Function):
         A = DeviceCSR(pattern.row_ptr, pattern.col_idx, val.detach().contiguous(), pattern.n,
                       pattern.nnz)
         x = torch.zeros_like(b)
-        _accept(assg_solve(handle, A, b.detach().contiguous(), x, opts), "forward")
+        _accept(assg_solve(handle, A, b.detach().contiguous(), x, opts), "forward", opts.tol)
         ctx.A, ctx.handle, ctx.opts = A, handle, opts
         ctx.save_for_backward(x)
         return x
@@ -55,7 +64,7 @@ class _Solve(torch.autograd.Function):
         lam = torch.zeros_like(x)
         g = gx.detach().contiguous()
         if torch.count_nonzero(g).item() > 0:
-            _accept(assg_solve(h, A, g, lam, ctx.opts), "adjoint")
+            _accept(assg_solve(h, A, g, lam, ctx.opts), "adjoint", ctx.opts.tol)
         gval = None
         if ctx.needs_input_grad[0]:
             gval = torch.empty_like(A.val)

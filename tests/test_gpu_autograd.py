@@ -97,8 +97,11 @@ def test_gradient_central_differences_full_size(env):
     step 1e-5 of the norms.  The difference quotient carries the truncation
     error O(h^2) and the solve error of the two losses divided by h; 1e-4
     relative covers both here.  The adjoint right-hand side 2 (x - t) is not
-    solvable to 1e-12 in FP64 by CG on this matrix (plain HSCG also stops near
-    2e-12): the solver reports STAGNATED there and returns its iterate."""
+    solvable to 1e-12 in FP64 by CG on this matrix: the forward solve must
+    converge, and the adjoint must reach 1e-12 or at least the relative
+    residual that plain HSCG on the GPU attains on the same right-hand side
+    (when it stops above 1e-12 the solver reports STAGNATED, warns, and
+    returns its iterate)."""
     torch, L = env
     from paper_1908_04081_amd.autograd import solve
     pr = P.make_config("varcoef7_128")
@@ -116,12 +119,25 @@ def test_gradient_central_differences_full_size(env):
         x = solve(pat, val, bv, handle=h, **opts)
         return ((x - t) ** 2).sum()
 
+    import warnings
+
+    from paper_1908_04081_amd.autograd import SolveStagnated, last_info
     val = val0.clone().requires_grad_(True)
     bt = b0.clone().requires_grad_(True)
-    loss(val, bt).backward()
-    from paper_1908_04081_amd.autograd import last_info
-    assert last_info["forward"]["relres_true"] <= 1e-11
-    assert last_info["adjoint"]["relres_true"] <= 1e-11
+    with warnings.catch_warnings(record=True) as caught:
+        warnings.simplefilter("always")
+        x = solve(pat, val, bt, handle=h, **opts)
+        ((x - t) ** 2).sum().backward()
+    fi, ai = last_info["forward"], last_info["adjoint"]
+    assert fi["outcome"] == L.CONVERGED and fi["relres_true"] <= 1e-12, fi
+    g = (2.0 * (x.detach() - t)).contiguous()
+    lam = torch.zeros_like(g)
+    hi = L.assg_hscg_solve(h, pat, g, lam, 1e-12, 0)
+    print(f"adjoint: {ai['outcome_name']} {ai['relres_true']:.3e}; HSCG on the same "
+          f"right-hand side: {hi['outcome_name']} {hi['relres_true']:.3e}", flush=True)
+    assert ai["relres_true"] <= max(1e-12, hi["relres_true"]), (ai, hi)
+    stagnated = [w for w in caught if issubclass(w.category, SolveStagnated)]
+    assert bool(stagnated) == (ai["outcome"] == L.STAGNATED)
     gval, gb = val.grad.cpu().numpy(), bt.grad.cpu().numpy()
     worst = 0.0
     with torch.no_grad():

@@ -171,11 +171,22 @@ def test_controller_replays_oracle_loops(env, name, basis, sigma):
     breaks = sum(1 for rec in tr if rec["broke"])
     if name == "geom_100":
         assert breaks >= 5, breaks
+    ties = 0
     for k, rec in enumerate(tr):
         sbar = rec["sbar"]
         G = to_interleaved_matrix(rec["G"], sbar)
         S = block_state_from_oracle(L, rec["state_in"])
         res = L.assg_block_controller(h, G, sbar, nb, 1e-10, basis, sigma, S)
+        if res.stilde != rec["stilde"]:
+            # only where the deciding leading block of G is numerically
+            # singular (smallest eigenvalue within rounding of 0, where the
+            # sign, and so kappa = inf or not, is the eigensolver's): both
+            # choices are correct and the rest of the loop differs
+            l = min(res.stilde, rec["stilde"]) + 1
+            ev = np.linalg.eigvalsh(rec["G"][np.ix_(O.sub_indices(sbar, l), O.sub_indices(sbar, l))])
+            assert ev[0] <= 64 * 2.0 ** -53 * (2 * l + 1) * ev[-1], (k, res.stilde, rec["stilde"], ev[0], ev[-1])
+            ties += 1
+            continue
         assert res.stilde == rec["stilde"], (k, res.stilde, rec["stilde"])
         assert res.sk == rec["sk"], (k, res.sk, rec["sk"], rec["broke"])
         assert bool(res.candidate) == bool(rec["candidate"])
@@ -208,6 +219,10 @@ def test_controller_replays_oracle_loops(env, name, basis, sigma):
                                            rtol=1e-11 + rt)
                 th = nxt["params"][0]
                 np.testing.assert_allclose(np.array(S.theta[:th.size]), th, rtol=1e-11 + rt)
+    assert ties <= len(tr) // 2, ties
+    if name == "geom_100":
+        compared_breaks = breaks - ties
+        assert compared_breaks >= 3, (breaks, ties)
 
 
 @pytest.mark.parametrize("name", ["poisson3d_21", "ragged_3001"])
