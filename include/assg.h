@@ -271,6 +271,25 @@ assg_status_t assg_solve_forced_schedule(assg_handle_t h, const assg_csr_t* A, c
                                          int64_t nsk, void* workspace, size_t workspace_bytes,
                                          assg_info_t* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): assg_solve
+ * with no workspace argument and no allocation of any kind inside the call.
+ * The basis and the Gram partials live in a static device array of
+ * ASSG_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on holds
+ * until the process ends; the call refuses (ASSG_ERR_INVALID_ARG) a system
+ * whose assg_workspace_size(n, opts.s_max) exceeds it (about 354,000 rows at
+ * s_max = 10), and opts.record_trace and opts.time_kernels must be 0.  The
+ * handle (assg_create) and the analysis (assg_analyze) allocate as usual, so
+ * they come before.  The outer loops are launched one by one (no graph
+ * capture), with the same kernels and results as assg_solve.  Every call on
+ * a GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * handles, other host threads, other streams) race and must not be issued;
+ * nothing in the array needs to start at zero. */
+#define ASSG_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define ASSG_MAX_DEVICES 64   /* devices with a scratch address table entry */
+assg_status_t assg_solve_noalloc(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                                 const assg_opts_t* opts, assg_info_t* info);
+
 /* Algorithm 1 (HSCG) on the GPU: one SpMV with a fused p^T A p partial sum,
  * one update kernel with a fused r^T r partial sum and one direction update
  * per iteration; stopping as for assg_solve (updated residual <= tol, then

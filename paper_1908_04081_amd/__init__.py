@@ -88,6 +88,7 @@ EXPORTS = [
     "assg_create", "assg_destroy", "assg_set_stream", "assg_basis_params",
     "assg_workspace_size", "assg_analyze", "assg_solve", "assg_hscg_solve", "assg_get_trace",
     "assg_spmv", "assg_basis_gram", "assg_block_controller", "assg_solve_forced_schedule",
+    "assg_solve_noalloc",
 ]
 
 _lib = None
@@ -116,6 +117,8 @@ def lib():
         "assg_analyze": (I32, [P, C.POINTER(AssgCsr)]),
         "assg_solve": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts), P, C.c_size_t,
                              C.POINTER(AssgInfo)]),
+        "assg_solve_noalloc": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts),
+                                     C.POINTER(AssgInfo)]),
         "assg_solve_forced_schedule": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts),
                                              C.POINTER(I32), I64, P, C.c_size_t,
                                              C.POINTER(AssgInfo)]),
@@ -302,6 +305,20 @@ def assg_solve(h: Handle, A: DeviceCSR, b, x, opts: AssgOpts | None = None, work
     _check(lib().assg_solve(h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"),
                             C.byref(opts), ws, wsb,
                             C.byref(info)), h.ptr)
+    return _info_dict(info)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def assg_solve_noalloc(h: Handle, A: DeviceCSR, b, x, opts: AssgOpts | None = None) -> dict:
+    """assg_solve with its workspace in the library's static per-device
+    scratch (no allocation inside the call; n limited by the scratch size)."""
+    opts = opts or assg_default_opts()
+    info = AssgInfo()
+    d = A.c()
+    _check(lib().assg_solve_noalloc(h.ptr, C.byref(d), _f64(b, A.n, "b"), _f64(x, A.n, "x"),
+                                    C.byref(opts), C.byref(info)), h.ptr)
     return _info_dict(info)
 
 

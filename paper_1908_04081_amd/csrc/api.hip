@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -311,6 +312,31 @@ assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes) {
   return ASSG_OK;
 }
 
+// Scratch of assg_solve_noalloc (basis and Gram partials of solves whose
+// callers cannot allocate).  Each GPU the library runs on holds its own copy
+// from the library's load until the process ends; in host code the name is
+// only a stand-in, so kernels get the address that hipGetSymbolAddress
+// returns for the current device, taken once per device in assg_create.
+static __device__ __align__(256) char scratch[ASSG_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[ASSG_MAX_DEVICES];
+
+static assg_status_t scratch_setup(assg_handle_t h) {
+  if (h->device < 0 || h->device >= ASSG_MAX_DEVICES)
+    return fail(h, ASSG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[h->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(h, ASSG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+    g_scratch_ptr[h->device] = p;
+  }
+  h->scratch = g_scratch_ptr[h->device];
+  return ASSG_OK;
+}
+
 assg_status_t assg_create(assg_handle_t* out, void* stream) {
   if (!out) return ASSG_ERR_INVALID_ARG;
   *out = nullptr;
@@ -332,6 +358,13 @@ assg_status_t assg_create(assg_handle_t* out, void* stream) {
   HIP_OR_FAIL(h, hipMalloc(&h->d_flag, sizeof(int32_t)));
   leja_table(h->leja, MAXS);
   for (int s = 1; s <= MAXS; ++s) h->gram_blocks[s] = last_gram_blocks(s, h->cus);
+  {
+    const assg_status_t st = scratch_setup(h);
+    if (st != ASSG_OK) {
+      assg_destroy(h);
+      return st;
+    }
+  }
   *out = h;
   return ASSG_OK;
 }
@@ -462,11 +495,29 @@ assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, co
 // form assg_solve_forced_schedule.
 static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
                                 const assg_opts_t* opts, const int32_t* forced, int64_t nsk,
-                                void* workspace, size_t workspace_bytes, assg_info_t* info) {
+                                void* workspace, size_t workspace_bytes, assg_info_t* info,
+                                bool noalloc = false) {
   if (!h) return ASSG_ERR_INVALID_ARG;
   if (!b || !x || !info) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   assg_status_t st = validate_opts(h, opts);
   if (st != ASSG_OK) return st;
+  if (noalloc) {
+    // nothing below may allocate: no trace buffer, no timing events, no graph
+    if (opts->record_trace || opts->time_kernels)
+      return fail(h, ASSG_ERR_INVALID_ARG,
+                  "assg_solve_noalloc: record_trace and time_kernels must be 0");
+    st = check_analyzed(h, A);
+    if (st != ASSG_OK) return st;
+    const size_t need = ws_layout(A->n, opts->s_max).total;
+    if (need > ASSG_NOALLOC_SCRATCH_BYTES)
+      return fail(h, ASSG_ERR_INVALID_ARG,
+                  "assg_solve_noalloc: n = " + std::to_string(A->n) + " at s_max = " +
+                      std::to_string(opts->s_max) + " needs " + std::to_string(need) +
+                      " bytes of scratch; the limit is " +
+                      std::to_string((size_t)ASSG_NOALLOC_SCRATCH_BYTES));
+    workspace = h->scratch;
+    workspace_bytes = ASSG_NOALLOC_SCRATCH_BYTES;
+  }
   st = check_analyzed(h, A);
   if (st != ASSG_OK) return st;
   if (overlap(b, x, A->n)) return fail(h, ASSG_ERR_INVALID_ARG, "b and x overlap");
@@ -544,6 +595,7 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
 
   // per-kernel timing: events bracket each matrix-powers launch of a loop
   const bool timing = opts->time_kernels != 0;
+  const bool eager = timing || noalloc;   // kernels launched one by one, no graph
   struct Timed { int64_t loop; int kind; size_t ev; };   // kind 0: sweep1, 1: sweep>=2, 2: last+gram
   std::vector<Timed> timed;
   size_t evn = 0;
@@ -551,7 +603,7 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
   int64_t n_sweep = 0, n_sweep1 = 0, n_last = 0;
 
   int32_t status = ST_RUNNING;
-  if (!timing) {
+  if (!eager) {
     // outer loops replayed from a captured graph of LOOPS_PER_GRAPH loops
     constexpr int LOOPS_PER_GRAPH = 4;
     const std::vector<const void*> key{A->row_ptr, A->col_idx, A->val, b, x, base, h->d_trace,
@@ -584,7 +636,7 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
   // with kernel timing: eager launches, events around each matrix-powers launch
   int64_t enqueued = 0;
   int batch = 1;
-  while (timing) {
+  while (eager) {
     timed.clear();
     evn = 0;
     for (int bi = 0; bi < batch; ++bi, ++enqueued) {
@@ -661,6 +713,11 @@ assg_status_t assg_solve(assg_handle_t h, const assg_csr_t* A, const double* b, 
                          const assg_opts_t* opts, void* workspace, size_t workspace_bytes,
                          assg_info_t* info) {
   return solve_impl(h, A, b, x, opts, nullptr, 0, workspace, workspace_bytes, info);
+}
+
+assg_status_t assg_solve_noalloc(assg_handle_t h, const assg_csr_t* A, const double* b, double* x,
+                                 const assg_opts_t* opts, assg_info_t* info) {
+  return solve_impl(h, A, b, x, opts, nullptr, 0, nullptr, 0, info, true);
 }
 
 assg_status_t assg_solve_forced_schedule(assg_handle_t h, const assg_csr_t* A, const double* b,

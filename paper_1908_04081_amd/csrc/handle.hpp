@@ -25,6 +25,7 @@ struct assg_handle_s {
   assg_trace_t* d_trace = nullptr;
   int64_t trace_cap = 0;
   int64_t trace_count = 0;
+  void* scratch = nullptr;       // this device's no-alloc scratch (device address)
   int32_t* d_forced = nullptr;   // schedule of assg_solve_forced_schedule
   int64_t forced_cap = 0;
   void* ws = nullptr;            // owned workspace
