@@ -291,11 +291,17 @@ def bandwidth_ceilings(torch, dev):
     read_t, _ = bwprobe.read_gbps(big, nontemporal=False)
     copy, ms_c = bwprobe.copy_gbps(big, dst)
     del dst
-    small = big[: 1 << 24]                                              # 128 MiB
-    mall, _ = bwprobe.read_gbps(small, nontemporal=False, iters=50)
-    del big, small
+    # ordinary loads of buffers of growing size read again and again: the
+    # 4 MB L2 of each XCD (every workgroup index lands on the same XCD on
+    # every pass), the 256 MB Infinity Cache, then HBM
+    reread = {}
+    for mib in (8, 32, 64, 128, 192, 512):
+        part = big[: mib << 17]
+        reread[str(mib)], _ = bwprobe.read_gbps(part, nontemporal=False, iters=50)
+        reread[str(mib)] = round(reread[str(mib)], 1)
+    del big
     out = {"stream_read_1GiB_GBps": round(read_nt, 1), "read_1GiB_cached_loads_GBps": round(read_t, 1),
-           "stream_copy_1GiB_GBps": round(copy, 1), "reread_128MiB_GBps": round(mall, 1),
+           "stream_copy_1GiB_GBps": round(copy, 1), "reread_GBps_by_MiB": reread,
            "peak_GBps": PEAK_HBM_GBPS,
            "note": "paper_1908_04081_amd/bwprobe kernels; copy counts read + write bytes"}
     print(f"[bench] ceilings: {out}", file=sys.stderr, flush=True)
