@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 64x64 Poisson workload (GPU and oracle times)")
     ap.add_argument("--no-probe", action="store_true", help="skip the bandwidth probes")
+    ap.add_argument("--sizes", type=str, default="",
+                    help="only a size sweep of the 7-point workload, e.g. 32,64,128 (sides)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU (its path on one GPU's share of the "
@@ -126,6 +128,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sizes:
+        print(json.dumps({"size_sweep": bench_sizes(L, P, torch, [int(v) for v in
+                                                                  args.sizes.split(",")],
+                                                    args.warmup, args.steps)}))
+        return
     ceilings = None if args.no_probe else bandwidth_ceilings(torch, dev)
     t0 = time.perf_counter()
     pr = P.make_config("poisson3d_256", size=args.size)
@@ -277,6 +284,39 @@ def main():
     out.update(extra)
     print(json.dumps(out))
     L.assg_destroy(h)
+
+
+def bench_sizes(L, P, torch, sides, warmup, steps):
+    """The 7-point Poisson workload (same recipe, b = A x*, tol 1e-10,
+    sigma = 10) at other grid sides: adaptive s-step CG with both bases and
+    HSCG, each warm-up then --steps timed solves on the production path
+    (median wall time)."""
+    rows = []
+    for side in sides:
+        pr = P.make_config("poisson3d_256", size=side)
+        A = L.csr_to_device(pr.A)
+        b = torch.from_numpy(pr.b).cuda()
+        x = torch.zeros_like(b)
+        h = L.assg_create()
+        L.assg_analyze(h, A)
+        row = {"side": side, "n": pr.n}
+        for m in ("chebyshev", "newton", "hscg"):
+            def run(m=m):
+                x.zero_()
+                if m == "hscg":
+                    return L.assg_hscg_solve(h, A, b, x, 1e-10, 0)
+                return L.assg_solve(h, A, b, x, L.assg_default_opts(s_max=10, tol=1e-10, basis=m))
+            t, inf = time_solves(run, warmup, steps, torch)
+            row[m + "_ms"] = round(1e3 * float(np.median(t)), 3)
+            row[m + "_outer"] = inf["outer_iters"]
+            row[m + "_iters"] = inf["total_iters"]
+        row["chebyshev_speedup"] = round(row["hscg_ms"] / row["chebyshev_ms"], 3)
+        row["newton_speedup"] = round(row["hscg_ms"] / row["newton_ms"], 3)
+        L.assg_destroy(h)
+        print(f"[bench] {side}^3: chebyshev {row['chebyshev_ms']} ms, newton {row['newton_ms']} ms, "
+              f"hscg {row['hscg_ms']} ms", file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
 
 
 def bandwidth_ceilings(torch, dev):

@@ -168,8 +168,23 @@ __device__ __forceinline__ double gmv(const double* grow, double v) {
   return s;
 }
 
-constexpr int CTL_WAVES = 8;   // waves estimating the leading blocks (largest first)
+constexpr int CTL_WAVES = 12;  // wave 0: the inner loop; the others: kappa of the leading blocks
 
+// Scalars of the inner loop after each step (one record per step).
+enum StepScalar {
+  SS_RGR, SS_PHI, SS_PSI, SS_LMIN, SS_LMAX, SS_C, SS_ALPHA, SS_BETA, SS_RHO,
+  SS_MXO, SS_MXH, SS_MXZ, SS_MNO, SS_MNA, SS_MND, SS_MNG, SS_MNH, SS_N
+};
+// How the speculative inner loop ended at its last recorded step.
+enum StepEvent { EV_NONE = 0, EV_BREAKDOWN, EV_DIVERGED_DEN, EV_DIVERGED, EV_CANDIDATE };
+
+// Inner step j of Algorithm 5 works in span Y_{k,j+2} only: its coordinate
+// vectors have support on the leading 2j+1 (p') and 2j+3 (r') coordinates,
+// so it never reaches the last P and R columns of Y_{k,s~} (whose images B
+// drops) for j < s~, and its result does not depend on s~.  Wave 0 runs the
+// steps on the whole basis (s-bar levels) while the other waves estimate
+// kappa; once s~ is known, the break (4.7) and the stopping test pick s_k
+// among the recorded steps.
 __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__ ctls,
                                                      assg_trace_t* __restrict__ trace) {
   Ctl* __restrict__ ctl = ctls + blockIdx.x;   // one workgroup per system
@@ -179,8 +194,12 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   __shared__ double sDE[MAXS][2][MAXC];
   __shared__ double sKappa[MAXS + 2];
   __shared__ double sTh[MAXS], sGa[MAXS], sMu[MAXS];
+  __shared__ double sVec[MAXS][3][MAXC];      // x', r', p' after each step
+  __shared__ double sStep[MAXS][SS_N];        // scalars after each step
+  __shared__ int sEvent[2];                   // steps recorded, event of the last one
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nwaves = blockDim.x >> 6;
   const int sbar = ctl->sbar;
   const int nc = 2 * sbar + 1;
   for (int i = tid; i < MAXC * MAXC; i += blockDim.x) {
@@ -195,52 +214,158 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   if (tid < MAXS + 2) sKappa[tid] = INFINITY;
   __syncthreads();
 
-  // ---- kappa(Y_{k,l}) for l = 1..sbar, largest blocks first: wave w takes
-  // l = sbar - w, then l = sbar - 15 + w (snake order balances the waves)
-  for (int pass = 0; pass < 2; ++pass) {
-    const int l = (pass == 0) ? sbar - wave : sbar - (2 * CTL_WAVES - 1) + wave;
-    if (l < 1 || (pass == 1 && l > sbar - CTL_WAVES)) continue;
-    const int n = 2 * l + 1;
-    double* T = sScr + scratch_offset(l) * MAXC;
-    for (int i = lane; i < n * MAXC; i += 64) {
-      const int a = i / MAXC, b = i % MAXC;
-      T[i] = (b < n) ? sG[a * MAXC + b] : 0.0;
+  const double u = UNIT_ROUNDOFF;
+  const double nb = ctl->nb, tol = ctl->tol;
+  const double c_in = ctl->c;
+  const int variant = ctl->variant;
+  const bool forced = ctl->forced_sk && (int64_t)ctl->k < ctl->forced_len;
+  const int64_t m = ctl->m;
+  const double rGr0 = fmax(sG[1 * MAXC + 1], 0.0);
+
+  if (wave == 0) {
+    // ---- the inner loop on the whole basis (interleaved coordinates; lane i
+    // owns coordinate i and row i of G); products are masked to the step's
+    // support, so rows of G past it never enter a sum
+    double grow[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) grow[c] = (lane < nc && c < nc) ? sG[lane * MAXC + c] : 0.0;
+    double vp = (lane == 0) ? 1.0 : 0.0;
+    double vr = (lane == 1) ? 1.0 : 0.0;
+    double vx = 0.0;
+    double rGr = rGr0;
+    double phi = sqrt(rGr) / nb;
+    double c = c_in;
+    double psi = ctl->psi;
+    double lmin = ctl->lmin, lmax = ctl->lmax;
+    double alpha_prev = ctl->alpha_prev, beta_prev = ctl->beta_prev;
+    double mx_omega = ctl->mx_omega, mx_h = ctl->mx_h, mx_zeta = ctl->mx_zeta;
+    double mn_omega = ctl->mn_omega, mn_a = ctl->mn_a, mn_d = ctl->mn_d, mn_g = ctl->mn_g,
+           mn_h = ctl->mn_h;
+    int steps = 0, event = EV_NONE;
+    for (int j = 0; j < sbar; ++j) {
+      const int sup = 2 * j + 3;                              // support of B p' and r'_{j+1}
+      const double bp = apply_B(vp, sbar, lane, sTh, sGa, sMu);
+      const double den = wave_sum_dpp(lane < sup ? vp * gmv(grow, bp) : 0.0);
+      if (!isfinite(den)) { steps = j + 1; event = EV_DIVERGED_DEN; break; }
+      if (den <= 0.0 || rGr <= 0.0) { steps = j + 1; event = EV_BREAKDOWN; break; }
+      const double alpha = rGr / den;
+      const double q = (lane < nc) ? alpha * vp : 0.0;
+      vx += q;
+      const double rnew = (lane < nc) ? vr - apply_B(q, sbar, lane, sTh, sGa, sMu) : 0.0;
+      vr = rnew;
+      const double rGr_new =
+          fmax(wave_sum_dpp(lane < sup ? rnew * gmv(grow, rnew) : 0.0), 0.0);
+      const double beta = rGr_new / rGr;
+      vp = (lane < nc) ? rnew + beta * vp : 0.0;
+      rGr = rGr_new;
+      const double rho = sqrt(rGr) / nb;
+      phi = fmax(phi, rho);
+      psi = psi / (psi + beta);                               // (4.5)
+      const int64_t i = m + j;                                // global iteration index
+      const double zeta = 1.0 / sqrt(alpha);                  // (4.1)
+      if (i == 0) {
+        mx_omega = zeta * zeta; mx_h = 1.0; mx_zeta = zeta;   // Algorithm 3 start
+        mn_omega = 1.0 / (zeta * zeta); mn_a = mn_omega;      // Algorithm 4 start
+        mn_d = 0.0; mn_g = 0.0; mn_h = 1.0;
+      } else {
+        const double eta = sqrt(beta_prev / alpha_prev);
+        {  // Algorithm 3 step (a uses zeta_{l+1})
+          const double dd = mx_zeta * mx_zeta * eta * eta * mx_h;
+          const double a = eta * eta + zeta * zeta;
+          const double chi = sqrt((mx_omega - a) * (mx_omega - a) + 4.0 * dd);
+          const double h = (chi == 0.0) ? 0.0 : 0.5 * (1.0 - (mx_omega - a) / chi);
+          mx_omega = mx_omega + chi * h;
+          mx_h = h;
+          mx_zeta = zeta;
+        }
+        {  // Algorithm 4 step
+          const double dd = -(eta / zeta) * (mn_g * mn_d + mn_h * mn_a);
+          const double a = (eta * eta * mn_a + 1.0) / (zeta * zeta);
+          const double chi = sqrt((mn_omega - a) * (mn_omega - a) + 4.0 * dd * dd);
+          const double h =
+              (chi == 0.0) ? 0.0 : sqrt(fmax(0.0, 0.5 * (1.0 - (mn_omega - a) / chi)));
+          mn_omega = mn_omega + chi * h * h;
+          mn_g = sqrt(fmax(0.0, 1.0 - h * h));
+          mn_h = fabs(h) * (dd < 0.0 ? -1.0 : 1.0);
+          mn_d = dd;
+          mn_a = a;
+        }
+        lmax = mx_omega;
+        lmin = 1.0 / mn_omega;
+        if (variant == ASSG_IMPROVED)
+          c = fmax(1.0, lmax * sqrt(psi / lmin));             // (4.6)
+        else if (variant == ASSG_IMPROVED_C_RATIO)
+          c = lmax / lmin;                                    // Section 5.1
+      }
+      alpha_prev = alpha;
+      beta_prev = beta;
+      if (lane < MAXC) {
+        sVec[j][0][lane] = vx;
+        sVec[j][1][lane] = vr;
+        sVec[j][2][lane] = vp;
+      }
+      if (lane == 0) {
+        double* r = sStep[j];
+        r[SS_RGR] = rGr; r[SS_PHI] = phi; r[SS_PSI] = psi; r[SS_LMIN] = lmin;
+        r[SS_LMAX] = lmax; r[SS_C] = c; r[SS_ALPHA] = alpha; r[SS_BETA] = beta; r[SS_RHO] = rho;
+        r[SS_MXO] = mx_omega; r[SS_MXH] = mx_h; r[SS_MXZ] = mx_zeta;
+        r[SS_MNO] = mn_omega; r[SS_MNA] = mn_a; r[SS_MND] = mn_d; r[SS_MNG] = mn_g;
+        r[SS_MNH] = mn_h;
+      }
+      steps = j + 1;
+      if (!isfinite(alpha) || !isfinite(beta)) { event = EV_DIVERGED; break; }
+      if (!forced && rho <= tol) { event = EV_CANDIDATE; break; }
     }
-    wave_lds_sync();
-    double kap = INFINITY;
-    double* dsh = sDE[l - 1][0];
-    double* esh = sDE[l - 1][1];
-    switch (l) {
-      case 1: kap = kappa_wave<3>(T, lane, dsh, esh); break;
-      case 2: kap = kappa_wave<5>(T, lane, dsh, esh); break;
-      case 3: kap = kappa_wave<7>(T, lane, dsh, esh); break;
-      case 4: kap = kappa_wave<9>(T, lane, dsh, esh); break;
-      case 5: kap = kappa_wave<11>(T, lane, dsh, esh); break;
-      case 6: kap = kappa_wave<13>(T, lane, dsh, esh); break;
-      case 7: kap = kappa_wave<15>(T, lane, dsh, esh); break;
-      case 8: kap = kappa_wave<17>(T, lane, dsh, esh); break;
-      case 9: kap = kappa_wave<19>(T, lane, dsh, esh); break;
-      case 10: kap = kappa_wave<21>(T, lane, dsh, esh); break;
-      case 11: kap = kappa_wave<23>(T, lane, dsh, esh); break;
-      case 12: kap = kappa_wave<25>(T, lane, dsh, esh); break;
-      case 13: kap = kappa_wave<27>(T, lane, dsh, esh); break;
-      case 14: kap = kappa_wave<29>(T, lane, dsh, esh); break;
-      case 15: kap = kappa_wave<31>(T, lane, dsh, esh); break;
-      default: kap = kappa_wave<33>(T, lane, dsh, esh); break;
+    if (lane == 0) {
+      sEvent[0] = steps;
+      sEvent[1] = event;
     }
-    if (lane == 0) sKappa[l] = kap;
+  } else {
+    // ---- kappa(Y_{k,l}) for l = 1..sbar: the blocks, largest first, dealt
+    // to waves 1.. in snake order (one block per wave up to s-bar = 11)
+    const int kw = nwaves - 1;
+    for (int idx = 0; idx < sbar; ++idx) {
+      const int round = idx / kw, pos = idx % kw;
+      const int owner = 1 + ((round & 1) ? kw - 1 - pos : pos);
+      if (owner != wave) continue;
+      const int l = sbar - idx;
+      const int n = 2 * l + 1;
+      double* T = sScr + scratch_offset(l) * MAXC;
+      for (int i = lane; i < n * MAXC; i += 64) {
+        const int a = i / MAXC, b = i % MAXC;
+        T[i] = (b < n) ? sG[a * MAXC + b] : 0.0;
+      }
+      wave_lds_sync();
+      double kap = INFINITY;
+      double* dsh = sDE[l - 1][0];
+      double* esh = sDE[l - 1][1];
+      switch (l) {
+        case 1: kap = kappa_wave<3>(T, lane, dsh, esh); break;
+        case 2: kap = kappa_wave<5>(T, lane, dsh, esh); break;
+        case 3: kap = kappa_wave<7>(T, lane, dsh, esh); break;
+        case 4: kap = kappa_wave<9>(T, lane, dsh, esh); break;
+        case 5: kap = kappa_wave<11>(T, lane, dsh, esh); break;
+        case 6: kap = kappa_wave<13>(T, lane, dsh, esh); break;
+        case 7: kap = kappa_wave<15>(T, lane, dsh, esh); break;
+        case 8: kap = kappa_wave<17>(T, lane, dsh, esh); break;
+        case 9: kap = kappa_wave<19>(T, lane, dsh, esh); break;
+        case 10: kap = kappa_wave<21>(T, lane, dsh, esh); break;
+        case 11: kap = kappa_wave<23>(T, lane, dsh, esh); break;
+        case 12: kap = kappa_wave<25>(T, lane, dsh, esh); break;
+        case 13: kap = kappa_wave<27>(T, lane, dsh, esh); break;
+        case 14: kap = kappa_wave<29>(T, lane, dsh, esh); break;
+        case 15: kap = kappa_wave<31>(T, lane, dsh, esh); break;
+        default: kap = kappa_wave<33>(T, lane, dsh, esh); break;
+      }
+      if (lane == 0) sKappa[l] = kap;
+    }
   }
   __syncthreads();
   if (wave != 0) return;
 
   // ---- s~ by (3.2) with the current c and relative ||r_m||
-  const double u = UNIT_ROUNDOFF;
-  const double nb = ctl->nb, tol = ctl->tol;
-  double c = ctl->c;
-  const double rGr0 = fmax(sG[1 * MAXC + 1], 0.0);
   const double rho_m = sqrt(rGr0) / nb;
-  const double thr = (rho_m > 0.0) ? tol / (c * u * rho_m) : INFINITY;
-  const int variant = ctl->variant;
+  const double thr = (rho_m > 0.0) ? tol / (c_in * u * rho_m) : INFINITY;
   int st = 1;
   for (int l = 1; l <= sbar; ++l) {
     if (sKappa[l] <= thr)
@@ -251,7 +376,6 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   if (variant == ASSG_FIXED_SSTEP) st = sbar;   // fixed s-step CG: the whole basis
   // a given schedule replaces (3.2), the break and the in-loop stopping test
   // in its loops; the loops after it decide for themselves
-  const bool forced = ctl->forced_sk && (int64_t)ctl->k < ctl->forced_len;
   const bool last_forced = forced && (int64_t)ctl->k + 1 == ctl->forced_len;
   if (forced) {
     const int32_t f = ctl->forced_sk[ctl->k];
@@ -259,96 +383,60 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   }
   const int n = 2 * st + 1;
 
-  // ---- inner loop (interleaved coordinates; lane i owns coordinate i and
-  // row i of G, zero beyond the 2 s~ + 1 leading ones)
-  double grow[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) grow[c] = (lane < n && c < n) ? sG[lane * MAXC + c] : 0.0;
-  double vp = (lane == 0) ? 1.0 : 0.0;
-  double vr = (lane == 1) ? 1.0 : 0.0;
-  double vx = 0.0;
-  double rGr = rGr0;
-  double phi = sqrt(rGr) / nb;
-  double psi = ctl->psi;
+  // ---- s_k: the first of breakdown/divergence, the stopping candidate, the
+  // break (4.7) after the step, or s~ steps; `last` is the record whose
+  // state the loop ends with (-1: the state on entry)
+  const int steps = sEvent[0], event = sEvent[1];
+  int sk = 0, candidate = 0, outcome = ST_RUNNING, last = -1;
+  for (int j = 0; j < st; ++j) {
+    sk = j + 1;
+    if (j == steps - 1 && (event == EV_BREAKDOWN || event == EV_DIVERGED_DEN)) {
+      outcome = (event == EV_BREAKDOWN) ? ASSG_BREAKDOWN : ASSG_DIVERGED;
+      break;
+    }
+    last = j;
+    if (j == steps - 1 && event == EV_DIVERGED) { outcome = ASSG_DIVERGED; break; }
+    if (j == steps - 1 && event == EV_CANDIDATE) { candidate = 1; break; }
+    if (forced) continue;
+    const double cj = sStep[j][SS_C];
+    if (variant <= ASSG_IMPROVED_C_ONE) {
+      if (j < st - 1 && sKappa[j + 2] >= tol / (cj * u * sStep[j][SS_PHI])) break;   // (4.7)
+    } else if (variant == ASSG_OLD_ADAPTIVE) {
+      // Algorithm 2: gamma = kappa(Y_{k,s~}) against the current residual
+      if (j < st - 1 && sKappa[st] >= tol / (cj * u * sStep[j][SS_RHO])) break;
+    }
+  }
+  // the last loop of a given schedule ends with the true-residual check
+  if (last_forced && outcome == ST_RUNNING) candidate = 1;
+
+  // the state the loop ends with
+  double rGr = rGr0, phi = sqrt(rGr0) / nb, c = c_in, psi = ctl->psi;
   double lmin = ctl->lmin, lmax = ctl->lmax;
   double alpha_prev = ctl->alpha_prev, beta_prev = ctl->beta_prev;
   double mx_omega = ctl->mx_omega, mx_h = ctl->mx_h, mx_zeta = ctl->mx_zeta;
   double mn_omega = ctl->mn_omega, mn_a = ctl->mn_a, mn_d = ctl->mn_d, mn_g = ctl->mn_g,
          mn_h = ctl->mn_h;
-  const int64_t m = ctl->m;
-  int sk = 0, candidate = 0, outcome = ST_RUNNING;
-  for (int j = 0; j < st; ++j) {
-    sk = j + 1;
-    const double bp = apply_B(vp, st, lane, sTh, sGa, sMu);
-    const double den = wave_sum_dpp(vp * gmv(grow, bp));
-    if (!isfinite(den)) { outcome = ASSG_DIVERGED; break; }
-    if (den <= 0.0 || rGr <= 0.0) { outcome = ASSG_BREAKDOWN; break; }
-    const double alpha = rGr / den;
-    const double q = (lane < n) ? alpha * vp : 0.0;
-    vx += q;
-    const double rnew = (lane < n) ? vr - apply_B(q, st, lane, sTh, sGa, sMu) : 0.0;
-    vr = rnew;
-    const double rGr_new = fmax(wave_sum_dpp(rnew * gmv(grow, rnew)), 0.0);
-    const double beta = rGr_new / rGr;
-    vp = (lane < n) ? rnew + beta * vp : 0.0;
-    rGr = rGr_new;
-    const double rho = sqrt(rGr) / nb;
-    phi = fmax(phi, rho);
-    psi = psi / (psi + beta);                               // (4.5)
-    const int64_t i = m + j;                                // global iteration index
-    const double zeta = 1.0 / sqrt(alpha);                  // (4.1)
-    if (i == 0) {
-      mx_omega = zeta * zeta; mx_h = 1.0; mx_zeta = zeta;   // Algorithm 3 start
-      mn_omega = 1.0 / (zeta * zeta); mn_a = mn_omega;      // Algorithm 4 start
-      mn_d = 0.0; mn_g = 0.0; mn_h = 1.0;
-    } else {
-      const double eta = sqrt(beta_prev / alpha_prev);
-      {  // Algorithm 3 step (a uses zeta_{l+1})
-        const double dd = mx_zeta * mx_zeta * eta * eta * mx_h;
-        const double a = eta * eta + zeta * zeta;
-        const double chi = sqrt((mx_omega - a) * (mx_omega - a) + 4.0 * dd);
-        const double h = (chi == 0.0) ? 0.0 : 0.5 * (1.0 - (mx_omega - a) / chi);
-        mx_omega = mx_omega + chi * h;
-        mx_h = h;
-        mx_zeta = zeta;
-      }
-      {  // Algorithm 4 step
-        const double dd = -(eta / zeta) * (mn_g * mn_d + mn_h * mn_a);
-        const double a = (eta * eta * mn_a + 1.0) / (zeta * zeta);
-        const double chi = sqrt((mn_omega - a) * (mn_omega - a) + 4.0 * dd * dd);
-        const double h = (chi == 0.0) ? 0.0 : sqrt(fmax(0.0, 0.5 * (1.0 - (mn_omega - a) / chi)));
-        mn_omega = mn_omega + chi * h * h;
-        mn_g = sqrt(fmax(0.0, 1.0 - h * h));
-        mn_h = fabs(h) * (dd < 0.0 ? -1.0 : 1.0);
-        mn_d = dd;
-        mn_a = a;
-      }
-      lmax = mx_omega;
-      lmin = 1.0 / mn_omega;
-      if (variant == ASSG_IMPROVED)
-        c = fmax(1.0, lmax * sqrt(psi / lmin));             // (4.6)
-      else if (variant == ASSG_IMPROVED_C_RATIO)
-        c = lmax / lmin;                                    // Section 5.1
-    }
-    alpha_prev = alpha;
-    beta_prev = beta;
-    if (lane == 0 && j < MAXS) {
-      ctl->alphas[j] = alpha;
-      ctl->betas[j] = beta;
-    }
-    if (!isfinite(alpha) || !isfinite(beta)) { outcome = ASSG_DIVERGED; break; }
-    if (forced) continue;
-    if (rho <= tol) { candidate = 1; break; }
-    if (variant <= ASSG_IMPROVED_C_ONE) {
-      if (j < st - 1 && sKappa[j + 2] >= tol / (c * u * phi)) break;   // (4.7), gamma_{j+1}
-    } else if (variant == ASSG_OLD_ADAPTIVE) {
-      // Algorithm 2: gamma = kappa(Y_{k,s~}) against the current residual
-      if (j < st - 1 && sKappa[st] >= tol / (c * u * rho)) break;
+  double vx = 0.0, vr = (lane == 1) ? 1.0 : 0.0, vp = (lane == 0) ? 1.0 : 0.0;
+  if (last >= 0) {
+    const double* r = sStep[last];
+    rGr = r[SS_RGR]; phi = r[SS_PHI]; psi = r[SS_PSI]; lmin = r[SS_LMIN]; lmax = r[SS_LMAX];
+    c = r[SS_C]; alpha_prev = r[SS_ALPHA]; beta_prev = r[SS_BETA];
+    mx_omega = r[SS_MXO]; mx_h = r[SS_MXH]; mx_zeta = r[SS_MXZ];
+    mn_omega = r[SS_MNO]; mn_a = r[SS_MNA]; mn_d = r[SS_MND]; mn_g = r[SS_MNG]; mn_h = r[SS_MNH];
+    if (lane < MAXC) {
+      vx = sVec[last][0][lane];
+      vr = sVec[last][1][lane];
+      vp = sVec[last][2][lane];
     }
   }
-
-  // the last loop of a given schedule ends with the true-residual check
-  if (last_forced && outcome == ST_RUNNING) candidate = 1;
+  {
+    // the recorded steps (a breakdown is found before its step's update)
+    const int rec = (event == EV_BREAKDOWN || event == EV_DIVERGED_DEN) ? steps - 1 : steps;
+    if (lane < MAXS && lane < rec) {
+      ctl->alphas[lane] = sStep[lane][SS_ALPHA];
+      ctl->betas[lane] = sStep[lane][SS_BETA];
+    }
+  }
 
   // ---- results
   if (lane < MAXC) {
@@ -374,7 +462,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       tr.m = m;
       tr.candidate = candidate;
       tr.flags = (outcome == ASSG_BREAKDOWN ? 1 : 0) | (outcome == ASSG_DIVERGED ? 2 : 0);
-      tr.c_in = ctl->c;
+      tr.c_in = c_in;
       tr.thr = thr;
       tr.rho_m = rho_m;
       tr.phi = phi;
@@ -418,7 +506,8 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
 }
 
 void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma, int nsys) {
-  const int waves = sigma < 1 ? 1 : (sigma < CTL_WAVES ? sigma : CTL_WAVES);
+  // one wave for the inner loop and up to CTL_WAVES - 1 for the kappa blocks
+  const int waves = sigma < 1 ? 2 : (sigma + 1 < CTL_WAVES ? sigma + 1 : CTL_WAVES);
   hipLaunchKernelGGL(k_controller, dim3(nsys), dim3(64 * waves), 0, s, ctl,
                      nsys == 1 ? trace : nullptr);
 }
