@@ -190,8 +190,9 @@ const char* assg_status_string(assg_status_t s);
 const char* assg_last_error(assg_handle_t h);
 
 /* sizeof of the public structs, in the order assg_opts_t, assg_info_t,
- * assg_trace_t, assg_block_state_t, assg_block_result_t, assg_csr_t; lets a
- * binding check its layout.  Host only.  Returns the count written (<= cap). */
+ * assg_trace_t, assg_block_state_t, assg_block_result_t, assg_csr_t,
+ * assg_tune_class_t; lets a binding check its layout.  Host only.  Returns
+ * the count written (<= cap). */
 int32_t assg_struct_sizes(int64_t* sizes, int32_t cap);
 
 /* Creates a handle on the current HIP device.  ``stream`` is a hipStream_t
@@ -314,10 +315,9 @@ assg_status_t assg_get_trace(assg_handle_t h, assg_trace_t* host_buf, int64_t ca
  * block-diagonal copy of the patterns (the systems' rows and columns
  * concatenated; values are copied again at every solve), cuts row blocks
  * that never straddle systems, and picks the row-block shape of the
- * CSR-stream kernels by timing a product with each candidate (at most
- * 256/128/64 rows and 2048/1024/512 nonzeros per block): see
- * assg_batch_tuning.  Replaces any previous batch of the handle; the single
- * solve's analysis is kept. */
+ * CSR-stream kernels for each size class of systems by timing products
+ * (or from the process cache): see assg_batch_tuning.  Replaces any
+ * previous batch of the handle; the single solve's analysis is kept. */
 assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t* A);
 
 /* Algorithm 5 on every system of the analyzed batch at once.  Each kernel
@@ -335,11 +335,27 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
                                const double* const* b, double* const* x, const assg_opts_t* opts,
                                assg_info_t* info);
 
-/* The row-block shape chosen by the last assg_batch_analyze (rows and
- * nonzeros per block, host) and the measured product time of each candidate
- * shape in microseconds (host array of 3: 256/2048, 128/1024, 64/512). */
-assg_status_t assg_batch_tuning(assg_handle_t h, int32_t* rows, int32_t* nnz_cap,
-                                double* candidate_us);
+/* The batch tuner.  Systems fall into size classes by rows (class 0: n <
+ * 4,096; 1: < 65,536; 2: < 1,048,576; 3: larger).  For each class present,
+ * assg_batch_analyze times one product over that class's systems with each
+ * candidate row-block shape (rows per block / nonzero cap: 256/2048,
+ * 256/1024, 128/2048, 128/1024, 64/1024, 64/512) and keeps the fastest; the
+ * choice is cached for the process by (class, average nonzeros per row of
+ * the class rounded to an integer), and a later analysis with the same key
+ * reuses it without timing. */
+#define ASSG_TUNE_CLASSES 4
+#define ASSG_TUNE_SHAPES 6
+typedef struct {
+  int32_t systems;      /* systems of the batch in this class (0: none)               */
+  int32_t rows;         /* chosen rows per block                                       */
+  int32_t nnz_cap;      /* chosen nonzeros per block                                   */
+  int32_t cached;       /* 1: taken from the process cache, candidate_us all 0         */
+  double candidate_us[ASSG_TUNE_SHAPES]; /* product time of each candidate shape (us)  */
+} assg_tune_class_t;
+
+/* The tuner's result for the last assg_batch_analyze: classes (host) receives
+ * ASSG_TUNE_CLASSES records, in class order. */
+assg_status_t assg_batch_tuning(assg_handle_t h, assg_tune_class_t* classes);
 
 /* ------------------------------------------------------- differentiation */
 

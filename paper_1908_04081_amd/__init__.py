@@ -81,7 +81,16 @@ class AssgBlockResult(C.Structure):
                 ("coef_r", C.c_double * MAX_COLS), ("coef_p", C.c_double * MAX_COLS)]
 
 
-_STRUCTS = [AssgOpts, AssgInfo, AssgTrace, AssgBlockState, AssgBlockResult, AssgCsr]
+TUNE_CLASSES = 4
+TUNE_SHAPES = [(256, 2048), (256, 1024), (128, 2048), (128, 1024), (64, 1024), (64, 512)]
+
+
+class AssgTuneClass(C.Structure):
+    _fields_ = [("systems", C.c_int32), ("rows", C.c_int32), ("nnz_cap", C.c_int32),
+                ("cached", C.c_int32), ("candidate_us", C.c_double * len(TUNE_SHAPES))]
+
+
+_STRUCTS = [AssgOpts, AssgInfo, AssgTrace, AssgBlockState, AssgBlockResult, AssgCsr, AssgTuneClass]
 
 EXPORTS = [
     "assg_default_opts", "assg_status_string", "assg_last_error", "assg_struct_sizes",
@@ -131,7 +140,7 @@ def lib():
         "assg_batch_solve": (I32, [P, I32, C.POINTER(AssgCsr), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_void_p), C.POINTER(AssgOpts),
                                    C.POINTER(AssgInfo)]),
-        "assg_batch_tuning": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]),
+        "assg_batch_tuning": (I32, [P, C.POINTER(AssgTuneClass)]),
         "assg_basis_gram": (I32, [P, C.POINTER(AssgCsr), P, P, I32, C.POINTER(D), C.POINTER(D),
                                   C.POINTER(D), P, C.POINTER(D)]),
         "assg_block_controller": (I32, [P, C.POINTER(D), I32, D, D, I32, I32,
@@ -141,8 +150,8 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    sizes = (C.c_int64 * 6)()
-    L.assg_struct_sizes(sizes, 6)
+    sizes = (C.c_int64 * len(_STRUCTS))()
+    L.assg_struct_sizes(sizes, len(_STRUCTS))
     for st, sz in zip(_STRUCTS, sizes):
         if C.sizeof(st) != sz:
             raise RuntimeError(f"ABI mismatch: {st.__name__} is {C.sizeof(st)} bytes here, "
@@ -222,8 +231,8 @@ def assg_workspace_size(n: int, s_max: int) -> int:
 
 
 def assg_struct_sizes():
-    sizes = (C.c_int64 * 6)()
-    k = lib().assg_struct_sizes(sizes, 6)
+    sizes = (C.c_int64 * len(_STRUCTS))()
+    k = lib().assg_struct_sizes(sizes, len(_STRUCTS))
     return list(sizes[:k])
 
 
@@ -386,14 +395,15 @@ def assg_batch_solve(h: Handle, As: list, bs: list, xs: list, opts: AssgOpts | N
     return [_info_dict(i) for i in infos]
 
 
-def assg_batch_tuning(h: Handle) -> dict:
-    """Row-block shape picked by the batch autotuner and each candidate's
-    measured product time (us)."""
-    rows, cap = C.c_int32(), C.c_int32()
-    us = (C.c_double * 3)()
-    _check(lib().assg_batch_tuning(h.ptr, C.byref(rows), C.byref(cap), us), h.ptr)
-    return {"rows": rows.value, "nnz_cap": cap.value,
-            "candidates_us": {"256x2048": us[0], "128x1024": us[1], "64x512": us[2]}}
+def assg_batch_tuning(h: Handle) -> list:
+    """The batch tuner's choice per size class (rows < 4096, < 65536,
+    < 1048576, larger): systems, rows per block, nonzero cap, whether it came
+    from the process cache, and each candidate shape's product time (us)."""
+    arr = (AssgTuneClass * TUNE_CLASSES)()
+    _check(lib().assg_batch_tuning(h.ptr, arr), h.ptr)
+    return [{"systems": t.systems, "rows": t.rows, "nnz_cap": t.nnz_cap, "cached": bool(t.cached),
+             "candidates_us": {f"{r}x{c}": t.candidate_us[i] for i, (r, c) in enumerate(TUNE_SHAPES)}}
+            for t in arr]
 
 
 def assg_csr_outer_on_pattern(h: Handle, A: DeviceCSR, u, v, alpha: float, out):

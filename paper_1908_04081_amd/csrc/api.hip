@@ -281,9 +281,10 @@ const char* assg_last_error(assg_handle_t h) { return h ? h->err.c_str() : ""; }
 int32_t assg_struct_sizes(int64_t* sizes, int32_t cap) {
   const int64_t s[] = {(int64_t)sizeof(assg_opts_t),        (int64_t)sizeof(assg_info_t),
                        (int64_t)sizeof(assg_trace_t),       (int64_t)sizeof(assg_block_state_t),
-                       (int64_t)sizeof(assg_block_result_t), (int64_t)sizeof(assg_csr_t)};
+                       (int64_t)sizeof(assg_block_result_t), (int64_t)sizeof(assg_csr_t),
+                       (int64_t)sizeof(assg_tune_class_t)};
   int32_t k = 0;
-  for (; k < cap && k < 6; ++k) sizes[k] = s[k];
+  for (; k < cap && k < 7; ++k) sizes[k] = s[k];
   return k;
 }
 

@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "handle.hpp"
@@ -36,12 +39,13 @@ CsrView batch_view(assg_handle_t h) {
   return v;
 }
 
-// Row blocks of every system for one block shape: global row starts, nonzero
-// starts and the system of each block; sys_blk[i] = first block of system i.
+// Row blocks of every system, system i cut with the shape shape[i] = (rows,
+// cap): global row starts, nonzero starts and the system of each block;
+// sys_blk[i] = first block of system i.
 void batch_blocks(const std::vector<std::vector<int32_t>>& rps, const std::vector<int64_t>& row0,
-                  const std::vector<int64_t>& nz0, int rows, int cap, std::vector<int32_t>& blk,
-                  std::vector<int32_t>& blke, std::vector<int32_t>& bsys,
-                  std::vector<int32_t>& sys_blk) {
+                  const std::vector<int64_t>& nz0, const std::vector<std::pair<int, int>>& shape,
+                  std::vector<int32_t>& blk, std::vector<int32_t>& blke,
+                  std::vector<int32_t>& bsys, std::vector<int32_t>& sys_blk) {
   blk.clear();
   blke.clear();
   bsys.clear();
@@ -49,7 +53,7 @@ void batch_blocks(const std::vector<std::vector<int32_t>>& rps, const std::vecto
   std::vector<int32_t> b;
   for (size_t i = 0; i < rps.size(); ++i) {
     const int64_t n = (int64_t)rps[i].size() - 1;
-    make_blocks(rps[i].data(), n, b, rows, cap);
+    make_blocks(rps[i].data(), n, b, shape[i].first, shape[i].second);
     for (size_t k = 0; k + 1 < b.size(); ++k) {
       blk.push_back((int32_t)(row0[i] + b[k]));
       blke.push_back((int32_t)(nz0[i] + rps[i][b[k]]));
@@ -61,6 +65,16 @@ void batch_blocks(const std::vector<std::vector<int32_t>>& rps, const std::vecto
   blk.push_back((int32_t)ntot);
   blke.push_back((int32_t)nnztot);
 }
+
+// Size class of a system by its rows (see assg_batch_tuning).
+int size_class(int64_t n) {
+  return n < 4096 ? 0 : n < 65536 ? 1 : n < 1048576 ? 2 : 3;
+}
+
+// The tuner's choices for this process: (class, average nonzeros per row)
+// -> (rows, cap).
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -86,7 +100,8 @@ extern "C" {
 
 // ---------------------------------------------------------------- batches
 static constexpr int BATCH_LOOPS_PER_GRAPH = 4;
-static const int TUNE_SHAPES[3][2] = {{256, 2048}, {128, 1024}, {64, 512}};
+static const int TUNE_SHAPES[ASSG_TUNE_SHAPES][2] = {{256, 2048}, {256, 1024}, {128, 2048},
+                                                     {128, 1024}, {64, 1024},  {64, 512}};
 
 assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t* A) {
   if (!h) return ASSG_ERR_INVALID_ARG;
@@ -150,49 +165,85 @@ assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipMemsetAsync(B.x, 0, (size_t)B.ntot * sizeof(double), h->stream));
 
-  // row-block shape: time one product with each candidate partition
+  // row-block shape per size class, the largest class first: time one
+  // product of the whole batch for each candidate shape of the class (the
+  // other classes keep their current shapes), unless the process cache has
+  // a choice for the class
   std::vector<int32_t> blk, blke, bsys, sys_blk;
-  double best = INFINITY;
-  int pick = 0;
-  for (int c = 0; c < 3; ++c) {
-    batch_blocks(rps, row0, nz0, TUNE_SHAPES[c][0], TUNE_SHAPES[c][1], blk, blke, bsys, sys_blk);
-    int32_t *dblk = nullptr, *dblke = nullptr;
-    HIP_OR_FAIL(h, hipMalloc(&dblk, blk.size() * sizeof(int32_t)));
-    HIP_OR_FAIL(h, hipMalloc(&dblke, blke.size() * sizeof(int32_t)));
-    HIP_OR_FAIL(h, hipMemcpyAsync(dblk, blk.data(), blk.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, h->stream));
-    HIP_OR_FAIL(h, hipMemcpyAsync(dblke, blke.data(), blke.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, h->stream));
-    CsrView v{};
-    v.n = B.ntot;
-    v.nnz = B.nnztot;
-    v.rp = B.rpc;
-    v.ci = B.cic;
-    v.va = B.vac;
-    v.blk = dblk;
-    v.blke = dblke;
-    v.nblk = (int32_t)blk.size() - 1;
-    launch_spmv(h->stream, v, B.x, B.b);   // warm-up
-    hipEvent_t e0 = pool_event(h, 0), e1 = pool_event(h, 1);
-    if (!e0 || !e1) return fail(h, ASSG_ERR_HIP, "event creation failed");
-    HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < 5; ++r) launch_spmv(h->stream, v, B.x, B.b);
-    HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
-    HIP_OR_FAIL(h, hipGetLastError());
-    HIP_OR_FAIL(h, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
-    B.tune_us[c] = 1e3 * ms / 5.0;
-    if (B.tune_us[c] < best) {
-      best = B.tune_us[c];
-      pick = c;
+  std::vector<std::pair<int, int>> shape(nsys, {SB_ROWS, SB_CAP});
+  for (int cl = ASSG_TUNE_CLASSES - 1; cl >= 0; --cl) {
+    assg_tune_class_t& T = B.tune[cl];
+    T = assg_tune_class_t{};
+    std::vector<int> sel;
+    int64_t cn = 0, cnz = 0;
+    for (int i = 0; i < nsys; ++i)
+      if (size_class(A[i].n) == cl) {
+        sel.push_back(i);
+        cn += A[i].n;
+        cnz += A[i].nnz;
+      }
+    T.systems = (int32_t)sel.size();
+    if (sel.empty()) continue;
+    const std::pair<int, int> key{cl, (int)((cnz + cn / 2) / cn)};
+    std::pair<int, int> pick{SB_ROWS, SB_CAP};
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      const auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        pick = it->second;
+        cached = true;
+      }
     }
-    HIP_OR_FAIL(h, hipFree(dblk));
-    HIP_OR_FAIL(h, hipFree(dblke));
+    if (!cached) {
+      double best = INFINITY;
+      for (int c = 0; c < ASSG_TUNE_SHAPES; ++c) {
+        std::vector<std::pair<int, int>> sh(shape);
+        for (const int i : sel) sh[i] = {TUNE_SHAPES[c][0], TUNE_SHAPES[c][1]};
+        batch_blocks(rps, row0, nz0, sh, blk, blke, bsys, sys_blk);
+        int32_t *dblk = nullptr, *dblke = nullptr;
+        HIP_OR_FAIL(h, hipMalloc(&dblk, blk.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(h, hipMalloc(&dblke, blke.size() * sizeof(int32_t)));
+        HIP_OR_FAIL(h, hipMemcpyAsync(dblk, blk.data(), blk.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, h->stream));
+        HIP_OR_FAIL(h, hipMemcpyAsync(dblke, blke.data(), blke.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, h->stream));
+        CsrView v{};
+        v.n = B.ntot;
+        v.nnz = B.nnztot;
+        v.rp = B.rpc;
+        v.ci = B.cic;
+        v.va = B.vac;
+        v.blk = dblk;
+        v.blke = dblke;
+        v.nblk = (int32_t)blk.size() - 1;
+        launch_spmv(h->stream, v, B.x, B.b);   // warm-up
+        hipEvent_t e0 = pool_event(h, 0), e1 = pool_event(h, 1);
+        if (!e0 || !e1) return fail(h, ASSG_ERR_HIP, "event creation failed");
+        HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+        for (int r = 0; r < 5; ++r) launch_spmv(h->stream, v, B.x, B.b);
+        HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+        HIP_OR_FAIL(h, hipGetLastError());
+        HIP_OR_FAIL(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+        T.candidate_us[c] = 1e3 * ms / 5.0;
+        if (T.candidate_us[c] < best) {
+          best = T.candidate_us[c];
+          pick = {TUNE_SHAPES[c][0], TUNE_SHAPES[c][1]};
+        }
+        HIP_OR_FAIL(h, hipFree(dblk));
+        HIP_OR_FAIL(h, hipFree(dblke));
+      }
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tune_cache[key] = pick;
+    }
+    T.rows = pick.first;
+    T.nnz_cap = pick.second;
+    T.cached = cached ? 1 : 0;
+    for (const int i : sel) shape[i] = pick;
   }
-  B.rows = TUNE_SHAPES[pick][0];
-  B.cap = TUNE_SHAPES[pick][1];
-  batch_blocks(rps, row0, nz0, B.rows, B.cap, blk, blke, bsys, sys_blk);
+  batch_blocks(rps, row0, nz0, shape, blk, blke, bsys, sys_blk);
   std::vector<int32_t> cblk, csys, sys_chunk;
   make_chunks(sys_blk, h->gram_blocks[10], cblk, csys, sys_chunk);
   if (cblk.size() - 1 > 4096)
@@ -224,14 +275,11 @@ assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t
   return ASSG_OK;
 }
 
-assg_status_t assg_batch_tuning(assg_handle_t h, int32_t* rows, int32_t* nnz_cap,
-                                double* candidate_us) {
+assg_status_t assg_batch_tuning(assg_handle_t h, assg_tune_class_t* classes) {
   if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!classes) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
   if (h->bat.nsys < 1) return fail(h, ASSG_ERR_NOT_ANALYZED, "no batch analyzed");
-  if (rows) *rows = h->bat.rows;
-  if (nnz_cap) *nnz_cap = h->bat.cap;
-  if (candidate_us)
-    for (int c = 0; c < 3; ++c) candidate_us[c] = h->bat.tune_us[c];
+  for (int c = 0; c < ASSG_TUNE_CLASSES; ++c) classes[c] = h->bat.tune[c];
   return ASSG_OK;
 }
 

@@ -65,8 +65,7 @@ struct assg_handle_s {
     double *b = nullptr, *x = nullptr;         // concatenated right-hand sides / iterates
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    int rows = assg::SB_ROWS, cap = assg::SB_CAP;          // row-block shape chosen by the tuner
-    double tune_us[3] = {0, 0, 0};
+    assg_tune_class_t tune[ASSG_TUNE_CLASSES] = {};        // the tuner's choice per size class
     hipGraphExec_t graph = nullptr;            // captured outer loops
     int graph_sigma = 0;
   } bat;

@@ -197,7 +197,7 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   if (ctl->status != ST_RUNNING) return;
   constexpr int NT = 64 * W;
   constexpr int TS = SB_ROWS;
-  constexpr int TP = TS + 1;                 // padded level stride (LDS banks)
+  constexpr int TP = TS + 2;                 // padded level stride (LDS banks)
   constexpr int NL = (NC + 1) / 2;           // pair levels (the last holds P_sbar, 0)
   constexpr int NG = (NC + 15) / 16;         // 16-column groups
   constexpr int NB = NG * (NG + 1) / 2;      // accumulated 16 x 16 blocks
@@ -613,11 +613,14 @@ void launch_check(hipStream_t s, Ctl* ctl, assg_trace_t* trace, const CsrView& A
 }
 
 // ------------------------------------------------------------------ HSCG
-// Algorithm 1 with two kernels per iteration over the row blocks:
-//  k_h_spmv   p = r + beta p (evaluated at the gathered columns too, so no
-//             separate direction pass; p is double-buffered), w = A p and
-//             the p^T w sum -> alpha;
-//  k_h_update x += alpha p, r -= alpha w and the r^T r sum -> beta.
+// Algorithm 1, one iteration = seven launches over the row blocks (each
+// grid sum finished by a one-workgroup kernel in index order):
+//  k_h_spmv + k_fin_alpha    w = A p and the p^T w sum -> alpha;
+//  k_h_update + k_fin_beta   x += alpha p, r -= alpha w and the r^T r sum
+//                            -> beta;
+//  k_h_dir                   p = r + beta p;
+//  k_check + k_fin_check     the stopping test (the true residual when the
+//                            updated one reached tol).
 __global__ __launch_bounds__(256) void k_h_init(Ctl* ctl, CsrView A, const double* __restrict__ b,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ r, double* __restrict__ p,

@@ -43,10 +43,10 @@ def test_library_exports_every_declared_function():
 
 def test_struct_sizes_match_the_python_mirrors():
     L, lib = _lib()
-    sizes = (C.c_int64 * 6)()
-    assert lib.assg_struct_sizes(sizes, 6) == 6
+    sizes = (C.c_int64 * 7)()
+    assert lib.assg_struct_sizes(sizes, 7) == 7
     mirrors = [L.AssgOpts, L.AssgInfo, L.AssgTrace, L.AssgBlockState, L.AssgBlockResult,
-               L.AssgCsr]
+               L.AssgCsr, L.AssgTuneClass]
     assert [C.sizeof(m) for m in mirrors] == list(sizes)
 
 

@@ -110,13 +110,20 @@ def test_batched_workload_full_size(env):
     """64 shifted 2D Poisson systems, sides 32..512 (6.2M rows in all), random
     normal right-hand sides, tol 1e-10: every system converges with true
     relative residual <= 1e-10 recomputed on the host; the ten smallest
-    against the oracle; the tuner's pick is one of its candidates."""
+    against the oracle; the tuner reports every size class present with a
+    pick among its candidates (timed, or from the process cache)."""
     torch, L, h = env
     probs = P.make_batch()
     xs, infos = _run(torch, L, h, probs, s_max=10, tol=1e-10)
-    t = L.assg_batch_tuning(h)
-    assert (t["rows"], t["nnz_cap"]) in ((256, 2048), (128, 1024), (64, 512))
-    assert all(v > 0 for v in t["candidates_us"].values())
+    tune = L.assg_batch_tuning(h)
+    classes = [0 if pr.n < 4096 else 1 if pr.n < 65536 else 2 if pr.n < 1048576 else 3
+               for pr in probs]
+    for cl, t in enumerate(tune):
+        assert t["systems"] == classes.count(cl)
+        if t["systems"]:
+            assert (t["rows"], t["nnz_cap"]) in L.TUNE_SHAPES
+            us = list(t["candidates_us"].values())
+            assert all(v == 0 for v in us) if t["cached"] else all(v > 0 for v in us)
     for pr, xg, ig in zip(probs, xs, infos):
         assert ig["outcome"] == L.CONVERGED, (pr.name, ig)
         rel = np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b)
@@ -155,3 +162,27 @@ def test_batch_at_maximum_size(env):
         assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
     with pytest.raises(L.AssgError, match="nsys"):
         L.assg_batch_analyze(h, As + As[:1])
+
+
+def test_tuner_cache_reuses_choices(env):
+    """A second analysis of a batch with the same size classes and nonzeros
+    per row takes every class's shape from the process cache (no timing),
+    and the same shapes; the solve is unchanged."""
+    torch, L, h = env
+    probs = P.make_batch(count=6, lo=40, hi=300, seed=21)
+    As = [L.csr_to_device(pr.A) for pr in probs]
+    L.assg_batch_analyze(h, As)
+    first = L.assg_batch_tuning(h)
+    L.assg_batch_analyze(h, As)
+    second = L.assg_batch_tuning(h)
+    for a, b in zip(first, second):
+        assert a["systems"] == b["systems"]
+        if a["systems"]:
+            assert b["cached"] and (a["rows"], a["nnz_cap"]) == (b["rows"], b["nnz_cap"])
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = L.assg_batch_solve(h, As, bs, xs, L.assg_default_opts(s_max=10, tol=1e-10))
+    for pr, x, ig in zip(probs, xs, infos):
+        assert ig["outcome"] == L.CONVERGED
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(pr.b - pr.A @ xg) / np.linalg.norm(pr.b) <= 1e-10
