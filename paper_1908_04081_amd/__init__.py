@@ -16,6 +16,8 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libassg.so")
+# the same sources built with -DASSG_DEBUG (index checks in the kernels)
+DEBUG_LIB_PATH = os.path.join(_PKG, "libassg_debug.so")
 
 MAX_S = 16
 MAX_COLS = 2 * MAX_S + 1
@@ -103,15 +105,20 @@ EXPORTS = [
 _lib = None
 
 
-def lib():
-    """The loaded libassg.so; raises if it has not been built."""
+def load(path: str = LIB_PATH):
+    """Loads the library at ``path`` (LIB_PATH, or DEBUG_LIB_PATH for the
+    build with kernel index checks) for this process; must come before the
+    first call.  Returns the library."""
     global _lib
     if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"libassg.so not found at {LIB_PATH}: build it with "
+        if getattr(_lib, "_path", None) == path:
+            return _lib
+        raise RuntimeError(f"another library is already loaded ({_lib._path})")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{os.path.basename(path)} not found at {path}: build it with "
                            "`python -m paper_1908_04081_amd.build` (no CPU fallback exists)")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
+    L._path = path
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
         "assg_default_opts": (I32, [C.POINTER(AssgOpts)]),
@@ -158,6 +165,12 @@ def lib():
                                f"{sz} in the library")
     _lib = L
     return L
+
+
+def lib():
+    """The loaded library (libassg.so unless load() chose another); raises if
+    it has not been built."""
+    return _lib if _lib is not None else load(LIB_PATH)
 
 
 class AssgError(RuntimeError):

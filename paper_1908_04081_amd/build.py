@@ -33,8 +33,8 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src, extra):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, extra, objdir=BUILD):
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
     cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -42,25 +42,38 @@ def _compile(src, extra):
     return obj, r.stderr
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+DEBUG_LIB = os.path.join(PKG, "libassg_debug.so")
+DEBUG_BUILD = os.path.join(PKG, "_build_debug")
+
+
+def build(verbose: bool = False, extra=(), debug: bool = True) -> str:
+    """Builds libassg.so and, unless ``debug`` is false, libassg_debug.so
+    (the same sources with -DASSG_DEBUG: index checks in the kernels)."""
+    lib = _build_lib(LIB, BUILD, list(extra), verbose)
+    if debug:
+        _build_lib(DEBUG_LIB, DEBUG_BUILD, [*extra, "-DASSG_DEBUG"], verbose)
+    build_probe()
+    build_example()
+    return lib
+
+
+def _build_lib(out: str, objdir: str, extra: list, verbose: bool) -> str:
+    os.makedirs(objdir, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
+        results = list(ex.map(lambda s: _compile(s, extra, objdir), srcs))
     if verbose:
         for obj, err in results:
             if err.strip():
                 print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
            *[o for o, _ in results]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    build_probe()
-    build_example()
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 PROBE_DIR = os.path.join(PKG, "bwprobe")

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -168,6 +169,32 @@ bool zero_rhs(assg_handle_t h, double* x, int64_t n, assg_info_t* info, assg_sta
   info->relres_true = 0.0;
   info->relres_updated = 0.0;
   return true;
+}
+
+assg_status_t debug_verdict(assg_handle_t h) {
+  const int a = debug_code_take_kernels(h->stream);
+  const int b = debug_code_take_controller(h->stream);
+  if (a == 0 && b == 0) return ASSG_OK;
+  return fail(h, ASSG_ERR_HIP, "kernel debug check failed (row kernels: code " +
+                                   std::to_string(a) + ", controller: code " +
+                                   std::to_string(b) + ")");
+}
+
+void log_solve(const char* what, int64_t n, int sigma, const assg_info_t* info) {
+  static const bool on = [] {
+    const char* v = std::getenv("ASSG_LOG");
+    return v && v[0] == '1';
+  }();
+  if (!on) return;
+  static const char* names[] = {"CONVERGED", "STAGNATED", "DIVERGED", "BREAKDOWN", "MAX_ITER",
+                                "RUNNING"};
+  const int o = info->outcome;
+  std::fprintf(stderr,
+               "assg: %s n=%lld s_max=%d outcome=%s outer=%lld iters=%lld relres_true=%.3e "
+               "relres_updated=%.3e device_ms=%.3f\n",
+               what, (long long)n, sigma, (o >= 0 && o <= 5) ? names[o] : "?",
+               (long long)info->outer_iters, (long long)info->total_iters, info->relres_true,
+               info->relres_updated, info->solve_ms);
 }
 
 // Outer loops completed: a loop that ended in breakdown or divergence is
@@ -474,7 +501,7 @@ assg_status_t assg_spmv(assg_handle_t h, const assg_csr_t* A, const double* x, d
   launch_spmv(h->stream, Av, x, y);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  return ASSG_OK;
+  return debug_verdict(h);
 }
 
 assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, const double* u,
@@ -488,7 +515,7 @@ assg_status_t assg_csr_outer_on_pattern(assg_handle_t h, const assg_csr_t* A, co
   launch_outer_pattern(h->stream, Av, u, v, alpha, out);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  return ASSG_OK;
+  return debug_verdict(h);
 }
 
 
@@ -706,6 +733,10 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
   info->last_gram_ms = t_last;
   info->last_gram_launches = n_last;
   info->other_ms = timing ? std::max(0.0, (double)ms - t_sweep - t_sweep1 - t_last) : 0.0;
+  log_solve(noalloc ? "solve_noalloc" : (forced ? "solve_forced_schedule" : "solve"), n, sigma,
+            info);
+  st = debug_verdict(h);
+  if (st != ASSG_OK) return st;
   h->trace_count = opts->record_trace ? std::min<int64_t>(c->k, h->trace_cap) : 0;
   return ASSG_OK;
 }
@@ -819,7 +850,8 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   info->lambda_max_est = NAN;
   info->c_last = NAN;
   info->solve_ms = ms;
-  return ASSG_OK;
+  log_solve("hscg", n, 1, info);
+  return debug_verdict(h);
 }
 
 assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double* p,
@@ -864,7 +896,7 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   const int nc = 2 * s + 1;
   for (int a = 0; a < nc; ++a)
     for (int bb = 0; bb < nc; ++bb) G_out[a * nc + bb] = c->G[a * MAXC + bb];
-  return ASSG_OK;
+  return debug_verdict(h);
 }
 
 assg_status_t assg_block_controller(assg_handle_t h, const double* G, int32_t sbar, double nb,
@@ -957,7 +989,7 @@ assg_status_t assg_block_controller(assg_handle_t h, const double* G, int32_t sb
     state->gamma[l] = c->gamma[l];
     state->mu[l] = c->mu[l];
   }
-  return ASSG_OK;
+  return debug_verdict(h);
 }
 
 }  // extern "C"

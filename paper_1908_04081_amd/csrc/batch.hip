@@ -426,8 +426,9 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
     o.lambda_max_est = c->lmax;
     o.c_last = c->c;
     o.solve_ms = ms;
+    log_solve("batch system", B.n[i], opts->s_max, &o);
   }
-  return ASSG_OK;
+  return debug_verdict(h);
 }
 
 }  // extern "C"

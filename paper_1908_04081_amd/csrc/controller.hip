@@ -202,6 +202,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
   const int nwaves = blockDim.x >> 6;
   const int sbar = ctl->sbar;
   const int nc = 2 * sbar + 1;
+  ASSG_DCHECK(sbar >= 1 && sbar <= MAXS && sbar <= ctl->sigma && nwaves >= 2, 31);
   for (int i = tid; i < MAXC * MAXC; i += blockDim.x) {
     const int a = i / MAXC, b = i % MAXC;
     sG[i] = (a < nc && b < nc) ? ctl->G[a * MAXC + b] : 0.0;
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(64 * CTL_WAVES) void k_controller(Ctl* __restrict__
       if (j < st - 1 && sKappa[st] >= tol / (cj * u * sStep[j][SS_RHO])) break;
     }
   }
+  ASSG_DCHECK(st >= 1 && st <= sbar && sk <= st && last < steps && last < sk, 32);
   // the last loop of a given schedule ends with the true-residual check
   if (last_forced && outcome == ST_RUNNING) candidate = 1;
 
@@ -510,6 +512,29 @@ void launch_controller(hipStream_t s, Ctl* ctl, assg_trace_t* trace, int sigma, 
   const int waves = sigma < 1 ? 2 : (sigma + 1 < CTL_WAVES ? sigma + 1 : CTL_WAVES);
   hipLaunchKernelGGL(k_controller, dim3(nsys), dim3(64 * waves), 0, s, ctl,
                      nsys == 1 ? trace : nullptr);
+}
+
+// The first failed check of a debug build since the last call (0: none, or
+// a release build), cleared.
+int debug_code_take_controller(hipStream_t s) {
+#ifdef ASSG_DEBUG
+  int v = 0;
+  if (hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_debug_code), sizeof(int), 0,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -1;
+  if (v != 0) {
+    const int z = 0;
+    if (hipMemcpyToSymbolAsync(HIP_SYMBOL(g_debug_code), &z, sizeof(int), 0,
+                               hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return -1;
+  }
+  return v;
+#else
+  (void)s;
+  return 0;
+#endif
 }
 
 }  // namespace assg

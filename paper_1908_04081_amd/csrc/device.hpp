@@ -10,6 +10,23 @@
 
 namespace assg {
 
+// ------------------------------------------------------- debug builds
+// Built with -DASSG_DEBUG, the kernels check the partition and index
+// invariants they rely on and keep the first failed check's code in a
+// device word of their translation unit, which the host reads (and clears)
+// after each call; release builds compile the checks away.
+#ifdef ASSG_DEBUG
+static __device__ int g_debug_code;
+#define ASSG_DCHECK(cond, code)                               \
+  do {                                                        \
+    if (!(cond) && g_debug_code == 0) g_debug_code = (code);  \
+  } while (0)
+#else
+#define ASSG_DCHECK(cond, code) \
+  do {                          \
+  } while (0)
+#endif
+
 constexpr int WAVE = 64;
 
 // ---------------------------------------------------------------- loads
@@ -255,9 +272,12 @@ __device__ __forceinline__ void block_range(int32_t nblk, int32_t& b0, int32_t& 
 template <class V>
 __device__ __forceinline__ int32_t chunk_of(const V& A, int32_t& b0, int32_t& b1, int32_t& sys) {
   const int32_t c = xcd_logical(blockIdx.x, gridDim.x);
+  ASSG_DCHECK(c >= 0 && c < A.nchunk, 11);
   b0 = A.cblk[c];
   b1 = A.cblk[c + 1];
   sys = A.csys ? A.csys[c] : 0;
+  ASSG_DCHECK(b0 >= 0 && b0 <= b1 && b1 <= A.nblk, 12);
+  ASSG_DCHECK(sys >= 0 && sys < A.nsys, 13);
   return c;
 }
 template <class V>

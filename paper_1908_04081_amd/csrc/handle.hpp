@@ -106,6 +106,11 @@ assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o);
 void init_ctl(assg_handle_t h, Ctl* c, int mode);
 void apply_variant(Ctl* c, const assg_opts_t* o);
 int64_t completed_loops(const Ctl* c);
+// Debug builds: ASSG_ERR_HIP when a kernel check failed since the last call
+// (release builds: always ASSG_OK, no device access).
+assg_status_t debug_verdict(assg_handle_t h);
+// Host-side logging of finished solves to stderr when ASSG_LOG=1.
+void log_solve(const char* what, int64_t n, int sigma, const assg_info_t* info);
 hipEvent_t pool_event(assg_handle_t h, size_t i);
 void batch_release(assg_handle_t h);
 

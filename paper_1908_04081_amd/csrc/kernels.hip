@@ -37,16 +37,21 @@ struct BlockRows {
   bool own;
   int64_t row;
   __device__ __forceinline__ BlockRows(const CsrView& A, int32_t b) {
+    ASSG_DCHECK(b >= 0 && b < A.nblk, 1);
     r0 = A.blk[b];
     nr = A.blk[b + 1] - r0;
     e0 = A.blke[b];
     ne = A.blke[b + 1] - e0;
+    ASSG_DCHECK(r0 >= 0 && nr >= 1 && (int64_t)r0 + nr <= A.n, 2);
+    ASSG_DCHECK(e0 >= 0 && ne >= 0 && (int64_t)e0 + ne <= A.nnz, 3);
+    ASSG_DCHECK(nr <= SB_ROWS && (ne <= SB_CAP || nr == 1), 4);
     own = (int)threadIdx.x < nr;
     row = (int64_t)r0 + threadIdx.x;
     rs = re = 0;
     if (own) {
       rs = A.rp[row] - e0;
       re = A.rp[row + 1] - e0;
+      ASSG_DCHECK(rs >= 0 && rs <= re && re <= ne, 5);
     }
   }
 };
@@ -246,6 +251,10 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
     r.nr = kblk[b + 1] - r.r0;
     r.e0 = kblke[b];
     r.ne = kblke[b + 1] - r.e0;
+    ASSG_DCHECK(b >= 0 && b < A.nblk, 21);
+    ASSG_DCHECK(r.r0 >= 0 && r.nr >= 1 && r.nr <= TS && (int64_t)r.r0 + r.nr <= A.n, 22);
+    ASSG_DCHECK(r.e0 >= 0 && r.ne >= 0 && (int64_t)r.e0 + r.ne <= A.nnz &&
+                    (r.ne <= SB_CAP || r.nr == 1), 23);
   };
   auto own_range = [&](Rows& r) {   // vector loads, consumed after the next drain
     r.rs = r.re = 0;
@@ -885,6 +894,29 @@ void launch_export_Y(hipStream_t s, int64_t n, int sbar, const double2* pairs,
   const int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_export_Y, dim3((unsigned)nb), dim3(256), 0, s, n, sbar, pairs, plast, ld,
                      Y);
+}
+
+// The first failed check of a debug build since the last call (0: none, or
+// a release build), cleared.
+int debug_code_take_kernels(hipStream_t s) {
+#ifdef ASSG_DEBUG
+  int v = 0;
+  if (hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_debug_code), sizeof(int), 0,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -1;
+  if (v != 0) {
+    const int z = 0;
+    if (hipMemcpyToSymbolAsync(HIP_SYMBOL(g_debug_code), &z, sizeof(int), 0,
+                               hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return -1;
+  }
+  return v;
+#else
+  (void)s;
+  return 0;
+#endif
 }
 
 }  // namespace assg

@@ -93,4 +93,10 @@ void launch_pair_init(hipStream_t s, int64_t n, const double* p, const double* r
 void launch_export_Y(hipStream_t s, int64_t n, int sbar, const double2* pairs,
                      const double* plast, int64_t ld, double* Y);
 
+// Debug builds (-DASSG_DEBUG): the code of the first failed kernel check
+// since the last call, per translation unit (0: none; always 0 in release
+// builds; -1: reading it failed), cleared.
+int debug_code_take_kernels(hipStream_t s);
+int debug_code_take_controller(hipStream_t s);
+
 }  // namespace assg

@@ -41,6 +41,23 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
+def test_debug_build_exports_every_declared_function():
+    """libassg_debug.so (the same sources with -DASSG_DEBUG: index checks in
+    the kernels) exports the same ABI with the same struct layouts."""
+    L, _ = _lib()
+    if not os.path.exists(L.DEBUG_LIB_PATH):
+        from paper_1908_04081_amd import build
+        build.build()
+    dbg = C.CDLL(L.DEBUG_LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(dbg, n)]
+    assert not missing, missing
+    dbg.assg_struct_sizes.restype = C.c_int32
+    sizes = (C.c_int64 * 7)()
+    assert dbg.assg_struct_sizes(sizes, 7) == 7
+    assert [C.sizeof(m) for m in (L.AssgOpts, L.AssgInfo, L.AssgTrace, L.AssgBlockState,
+                                  L.AssgBlockResult, L.AssgCsr, L.AssgTuneClass)] == list(sizes)
+
+
 def test_struct_sizes_match_the_python_mirrors():
     L, lib = _lib()
     sizes = (C.c_int64 * 7)()

@@ -459,3 +459,50 @@ def test_new_analysis_replaces_cached_graphs(env):
         gh = L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
         assert gh["outcome"] == L.CONVERGED and abs(gh["total_iters"] - ih["iters"]) <= 1
         assert np.linalg.norm(x.cpu().numpy() - xh) / np.linalg.norm(xh) <= 1e-8
+
+
+def test_nan_in_rhs_diverges(env):
+    """A NaN in b reaches the Gram matrix in the first loop: DIVERGED with no
+    completed loop, for Algorithm 5 and HSCG, as in the oracle."""
+    torch, L, h = env
+    pr = _problem("poisson2d_45")
+    pr.b = pr.b.copy()
+    pr.b[7] = np.nan
+    _, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=10, tol=1e-10)
+    _, ig = _solve_gpu(torch, L, h, pr, s_max=10, tol=1e-10)
+    assert io["outcome"] == O.Outcome.DIVERGED and ig["outcome"] == L.DIVERGED, ig
+    assert ig["outer_iters"] == io["outer"] == 0
+    Ad = L.csr_to_device(pr.A)
+    L.assg_analyze(h, Ad)
+    b = torch.from_numpy(pr.b).cuda()
+    x = torch.zeros_like(b)
+    gh = L.assg_hscg_solve(h, Ad, b, x, 1e-10, 0)
+    _, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
+    assert gh["outcome"] == L.DIVERGED and ih["outcome"] == O.Outcome.DIVERGED
+
+
+def test_assg_log_prints_one_line_per_solve():
+    """ASSG_LOG=1 makes the library print one line per finished solve on
+    stderr (host side only); without it nothing is printed."""
+    import os
+    import subprocess
+    import sys
+    torch_cuda()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch, paper_1908_04081_amd as L, spd_problems as P\n"
+            "pr = P.make_config('poisson2d_64', size=20)\n"
+            "A = L.csr_to_device(pr.A); h = L.assg_create(); L.assg_analyze(h, A)\n"
+            "b = torch.from_numpy(pr.b).cuda(); x = torch.zeros_like(b)\n"
+            "L.assg_solve(h, A, b, x, L.assg_default_opts(tol=1e-10))\n"
+            "x.zero_(); L.assg_hscg_solve(h, A, b, x, 1e-10, 0)\n") % root
+    for flag, want in (("1", 2), ("0", 0)):
+        env = dict(os.environ, ASSG_LOG=flag)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                           text=True, timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        lines = [ln for ln in r.stderr.splitlines() if ln.startswith("assg: ")]
+        assert len(lines) == want, r.stderr[-2000:]
+        if want:
+            assert "assg: solve n=400" in lines[0] and "outcome=CONVERGED" in lines[0]
+            assert lines[1].startswith("assg: hscg n=400")
