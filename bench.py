@@ -32,10 +32,11 @@ COUNTER_FILE = os.path.join(ROOT, "profiles", "hbm_counters_poisson3d_256.txt")
 KERNEL_SOURCES = ["kernels.hip", "device.hpp", "launch.hpp", "ctl.hpp"]
 
 
-def measured_traffic():
-    """HBM bytes per k_sweep launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed counter summary of the 256^3 workload, or None when
-    the kernel sources no longer hash to the ones that were measured."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the sweep kernel ``kernel`` (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated) from the committed counter summary of the
+    256^3 workload, or None when the kernel sources no longer hash to the
+    ones that were measured."""
     import hashlib
     try:
         text = open(COUNTER_FILE).read()
@@ -47,21 +48,34 @@ def measured_traffic():
     if f"ctl.hpp): {digest}" not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic k_sweep per launch (bytes):"):
+        if line.startswith(f"traffic {kernel} per launch (bytes):"):
             return int(line.split(":")[1])
     return None
 
 
-def mpk_bytes(n: int, nnz: int, s: int, chebyshev: bool):
-    """Algorithmic HBM bytes of one outer loop's matrix powers + Gram (s
-    levels), and of one two-chain sweep at level >= 2.
+def matrix_bytes(A, fmt: str) -> int:
+    """|A|, the bytes one read of the matrix moves in the storage the kernels
+    use: CSR 12 nnz + 4 (n + 1) (FP64 values, int32 columns and row
+    pointers); diagonal storage 8 nd n (FP64 values, nd diagonals of n
+    positions, no indices)."""
+    n = A.shape[0]
+    if fmt == "dia":
+        rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.indptr))
+        nd = int(np.unique(A.indices.astype(np.int64) - rows).size)
+        return 8 * nd * n
+    return 12 * int(A.nnz) + 4 * (n + 1)
 
-    |A| = 12 nnz + 4 (n + 1) (FP64 values, int32 columns and row pointers).
+
+def mpk_bytes(n: int, abytes: int, s: int, chebyshev: bool):
+    """Algorithmic HBM bytes of one outer loop's matrix powers + Gram (s
+    levels), and of one two-chain sweep at level >= 2, for a matrix read of
+    ``abytes`` = |A| (matrix_bytes).
+
     Sweep l (1 <= l < s): |A| + read level l-1 pairs (16 n) + write level l
     pairs (16 n) + for l >= 2 with a mu term (Chebyshev) read level l-2 pairs
     (16 n).  Last sweep + Gram: |A| + read the s pair levels (16 s n) + write
     P_s (8 n)."""
-    A = 12 * nnz + 4 * (n + 1)
+    A = abytes
     sweep_ge2 = A + (48 if chebyshev else 32) * n
     sweep1 = A + 32 * n
     last = A + 16 * s * n + 8 * n
@@ -113,6 +127,8 @@ def main():
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 64x64 Poisson workload (GPU and oracle times)")
     ap.add_argument("--no-probe", action="store_true", help="skip the bandwidth probes")
+    ap.add_argument("--format", choices=["auto", "csr", "dia"], default="auto",
+                    help="storage of A for the matrix-powers kernels (assg_set_format)")
     ap.add_argument("--sizes", type=str, default="",
                     help="only a size sweep of the 7-point workload, e.g. 32,64,128 (sides)")
     args = ap.parse_args()
@@ -143,7 +159,11 @@ def main():
     b = torch.from_numpy(pr.b).to(dev)
     x = torch.zeros_like(b)
     h = L.assg_create()
+    L.assg_set_format(h, args.format)
     L.assg_analyze(h, A)
+    fmt = L.assg_get_format(h)
+    abytes = matrix_bytes(pr.A, fmt)
+    sweep_kernel = "k_sweep_dia" if fmt == "dia" else "k_sweep"
     sigma, tol = 10, 1e-10
     max_iters = 200000
 
@@ -205,7 +225,7 @@ def main():
     # matrix-powers launch on the library's stream (same kernels, launched
     # one by one instead of from the graph; bit-identical iterates)
     kt = solve("chebyshev", timing=True)
-    tot_b, sweep_b, sweep1_b, last_b = mpk_bytes(n, nnz, sigma, True)
+    tot_b, sweep_b, sweep1_b, last_b = mpk_bytes(n, abytes, sigma, True)
     sweep_avg_ms = kt["sweep_ms"] / max(kt["sweep_launches"], 1)
     achieved = sweep_b / (sweep_avg_ms * 1e-3) / 1e9
     lastg_avg_ms = kt["last_gram_ms"] / max(kt["last_gram_launches"], 1)
@@ -214,7 +234,7 @@ def main():
     mpk_gbps = tot_b / (mpk_time_ms * 1e-3) / 1e9
     if not args.no_compare:
         kn = solve("newton", timing=True)
-        _, sweep_nb, _, _ = mpk_bytes(n, nnz, sigma, False)
+        _, sweep_nb, _, _ = mpk_bytes(n, abytes, sigma, False)
         nav = kn["sweep_ms"] / max(kn["sweep_launches"], 1)
         methods["newton"]["sweep_avg_ms"] = round(nav, 4)
         methods["newton"]["sweep_GBps"] = round(sweep_nb / (nav * 1e-3) / 1e9, 1)
@@ -251,16 +271,16 @@ def main():
             "workload": f"poisson3d_{args.size}: 3-D 7-point Poisson {args.size}^3, scaled, "
                         "b = A x*, x* ~ U(-1,1) seed 102, x0 = 0",
             "n": n, "nnz": nnz, "method": "improved adaptive s-step CG", "basis": "chebyshev",
-            "s_max": sigma, "tol": tol,
+            "s_max": sigma, "tol": tol, "format": fmt, "matrix_bytes": abytes,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep (two-chain matrix-powers level, levels >= 2)",
+            "kernel": f"{sweep_kernel} (two-chain matrix-powers level, levels >= 2)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
-            "traffic": measured_traffic() if args.size == 256 else None,
+            "traffic": measured_traffic(sweep_kernel) if args.size == 256 else None,
             "bytes_per_launch": sweep_b,
             "avg_launch_ms": round(sweep_avg_ms, 5),
             "launches": kt["sweep_launches"],
@@ -299,7 +319,7 @@ def bench_sizes(L, P, torch, sides, warmup, steps):
         x = torch.zeros_like(b)
         h = L.assg_create()
         L.assg_analyze(h, A)
-        row = {"side": side, "n": pr.n}
+        row = {"side": side, "n": pr.n, "format": L.assg_get_format(h)}
         for m in ("chebyshev", "newton", "hscg"):
             def run(m=m):
                 x.zero_()
@@ -360,6 +380,7 @@ def bench_small(L, P, torch, warmup, steps):
     x = torch.zeros_like(b)
     h = L.assg_create()
     L.assg_analyze(h, A)
+    fmt = L.assg_get_format(h)
     opts = L.assg_default_opts(s_max=10, tol=1e-10, basis="chebyshev")
 
     def ss():
@@ -383,7 +404,7 @@ def bench_small(L, P, torch, warmup, steps):
         t = time.perf_counter()
         _, ih = O.hscg(pr.A, pr.b, pr.x0, tol=1e-10)
         th_o.append(time.perf_counter() - t)
-    out = {"n": pr.n, "nnz": int(pr.A.nnz), "gpu_sstep": summary(ts, i_s), "gpu_hscg": summary(th, i_h),
+    out = {"n": pr.n, "nnz": int(pr.A.nnz), "format": fmt, "gpu_sstep": summary(ts, i_s), "gpu_hscg": summary(th, i_h),
            "oracle_sstep": {"s_median": round(float(np.median(to)), 4), "s_min": round(min(to), 4),
                             "runs": 3, "outer_iters": io["outer"], "total_iters": io["iters"]},
            "oracle_hscg": {"s_median": round(float(np.median(th_o)), 4), "s_min": round(min(th_o), 4),
@@ -458,7 +479,7 @@ def bench_diffusion(L, P, torch, warmup, steps):
     x = torch.zeros_like(b)
     h = L.assg_create()
     L.assg_analyze(h, A)
-    out = {"n": pr.n, "nnz": int(pr.A.nnz)}
+    out = {"n": pr.n, "nnz": int(pr.A.nnz), "format": L.assg_get_format(h)}
     for basis in ("chebyshev", "newton", "hscg"):
         def run(basis=basis):
             x.zero_()
@@ -577,7 +598,8 @@ def bench_grad(L, P, torch):
         torch.cuda.synchronize()
         return t1 - t0, time.perf_counter() - t1, x.detach()
 
-    out = {"workload": "varcoef7_128 (N=2,097,152), tol 1e-12, sigma = 10, Chebyshev"}
+    out = {"workload": "varcoef7_128 (N=2,097,152), tol 1e-12, sigma = 10, Chebyshev",
+           "format": L.assg_get_format(h)}
     for growth in (10, 2):
         run(growth)
         fwd, bwd, x = run(growth)
@@ -606,30 +628,34 @@ def bench_grad(L, P, torch):
 
 def cpu_baseline(pr, sigma, tol, gpu_outer):
     """The oracle (unchanged) on a bounded sample of the same workload: its
-    first outer loops on the full problem, timed on the host and scaled by the
-    outer-loop count of a full solve."""
+    first outer loops on the full problem, timed on the host with every
+    library thread pool held to one thread (SciPy's CSR product is
+    single-threaded anyway), scaled by the outer-loop count of a full
+    solve."""
+    import contextlib
+
     import oracle as O
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_limits
+        one_thread = threadpool_limits(limits=1)
     except Exception:
-        blas_threads = 1
-    loops = 2
-    t0 = time.perf_counter()
-    _, info = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=sigma, tol=tol, basis="chebyshev",
-                                  max_outer=loops)
-    dt = time.perf_counter() - t0
+        one_thread = contextlib.nullcontext()
+    loops = 1
+    with one_thread:
+        t0, c0 = time.perf_counter(), time.process_time()
+        _, info = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=sigma, tol=tol, basis="chebyshev",
+                                      max_outer=loops)
+        dt, cpu = time.perf_counter() - t0, time.process_time() - c0
     per_loop = dt / max(info["outer"], 1)
     return {
         "value": round(per_loop * gpu_outer, 2),
         "unit": "s",
-        "cores": int(blas_threads),
+        "cores": 1,
         "kind": "oracle",
-        "sample": f"first {info['outer']} outer loops of the oracle's adaptive s-step CG on the "
-                  f"same {pr.n}-row problem ({dt:.1f} s, {per_loop:.2f} s per loop; each loop "
-                  f"builds the full sigma={sigma} basis), scaled by the GPU solve's {gpu_outer} "
-                  f"outer loops; scipy CSR SpMV is single-threaded, the Gram product uses "
-                  f"{blas_threads} BLAS threads",
+        "sample": f"first {info['outer']} outer loop(s) of the oracle's adaptive s-step CG on the "
+                  f"same {pr.n}-row problem ({dt:.1f} s wall, {cpu:.1f} s CPU, {per_loop:.2f} s "
+                  f"per loop; each loop builds the full sigma={sigma} basis), scaled by the GPU "
+                  f"solve's {gpu_outer} outer loops; BLAS and OpenMP pools held to one thread",
         "host_cpus": os.cpu_count(),
     }
 

@@ -49,7 +49,7 @@ typedef enum {
   ASSG_ERR_INVALID_ARG = -1,  /* bad pointer, size or option; nothing was enqueued   */
   ASSG_ERR_HIP = -2,          /* a HIP call failed; assg_last_error() has the text   */
   ASSG_ERR_ALLOC = -3,        /* device or pinned allocation failed                  */
-  ASSG_ERR_UNSUPPORTED = -4,  /* no usable gfx950 device                             */
+  ASSG_ERR_UNSUPPORTED = -4,  /* no usable gfx950 device, or a storage A does not fit */
   ASSG_ERR_NOT_ANALYZED = -5  /* n, nnz, row_ptr or col_idx differ from the last analysis */
 } assg_status_t;
 
@@ -234,6 +234,37 @@ assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes);
  * pattern changes (row_ptr and col_idx must not change between analysis
  * and solve); values may change freely between solves. */
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
+
+/* Storage the matrix-powers kernels read A from, chosen by the next
+ * assg_analyze of a single system (batches always read CSR):
+ *  - ASSG_FORMAT_AUTO (the default): diagonal storage when every entry of A
+ *    lies on one of at most 32 diagonals (i, i + off) and those diagonals
+ *    hold at most 15% more positions than A has entries (stencil matrices),
+ *    else CSR;
+ *  - ASSG_FORMAT_CSR: CSR always;
+ *  - ASSG_FORMAT_DIA: diagonal storage whatever its fill, or
+ *    ASSG_ERR_UNSUPPORTED from the analysis when some entry lies off 32
+ *    diagonals (the handle is then left with no analysis).
+ * The diagonal storage is the library's copy of A's values, n per diagonal
+ * (0 where A has no entry), allocated at analysis and refreshed from the CSR
+ * values at the start of every solve and assg_basis_gram call, so values
+ * may still change between calls.  It is read by the matrix-powers sweeps,
+ * the last sweep with the Gram partials and HSCG's product A p; the setup,
+ * the true-residual check, assg_spmv and the gradient scatter read CSR.
+ * Each row's products are added in column order as in the CSR kernels, so
+ * rows agree bit for bit; grid-wide sums agree too when both storages cut
+ * the rows into the same 256-row blocks (at most 8 entries per row), and up
+ * to rounding otherwise.  INVALID_ARG for another format value. */
+typedef enum {
+  ASSG_FORMAT_AUTO = 0,
+  ASSG_FORMAT_CSR = 1,
+  ASSG_FORMAT_DIA = 2
+} assg_format_t;
+assg_status_t assg_set_format(assg_handle_t h, int32_t format);
+
+/* The storage the last successful analysis chose (ASSG_FORMAT_CSR or
+ * ASSG_FORMAT_DIA); ASSG_ERR_NOT_ANALYZED when there is none. */
+assg_status_t assg_get_format(assg_handle_t h, int32_t* format);
 
 /* ------------------------------------------------------------- the solves */
 

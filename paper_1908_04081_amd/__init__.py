@@ -28,6 +28,8 @@ OUTCOME_NAMES = {0: "CONVERGED", 1: "STAGNATED", 2: "DIVERGED", 3: "BREAKDOWN", 
                  5: "RUNNING"}
 BASIS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 VARIANT = {"improved": 0, "improved_c_ratio": 1, "improved_c_one": 2, "old": 3, "fixed": 4}
+FORMAT = {"auto": 0, "csr": 1, "dia": 2}
+FORMAT_NAMES = {v: k for k, v in FORMAT.items()}
 
 
 class AssgCsr(C.Structure):
@@ -99,7 +101,7 @@ EXPORTS = [
     "assg_create", "assg_destroy", "assg_set_stream", "assg_basis_params",
     "assg_workspace_size", "assg_analyze", "assg_solve", "assg_hscg_solve", "assg_get_trace",
     "assg_spmv", "assg_basis_gram", "assg_block_controller", "assg_solve_forced_schedule",
-    "assg_solve_noalloc",
+    "assg_solve_noalloc", "assg_set_format", "assg_get_format",
 ]
 
 _lib = None
@@ -131,6 +133,8 @@ def load(path: str = LIB_PATH):
         "assg_basis_params": (I32, [I32, D, D, I32, C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
         "assg_workspace_size": (I32, [I64, I32, C.POINTER(C.c_size_t)]),
         "assg_analyze": (I32, [P, C.POINTER(AssgCsr)]),
+        "assg_set_format": (I32, [P, I32]),
+        "assg_get_format": (I32, [P, C.POINTER(I32)]),
         "assg_solve": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts), P, C.c_size_t,
                              C.POINTER(AssgInfo)]),
         "assg_solve_noalloc": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts),
@@ -310,6 +314,19 @@ def assg_set_stream(h: Handle, stream=None):
 def assg_analyze(h: Handle, A: DeviceCSR):
     d = A.c()
     _check(lib().assg_analyze(h.ptr, C.byref(d)), h.ptr)
+
+
+def assg_set_format(h: Handle, fmt: str = "auto"):
+    """Storage of A for the matrix-powers kernels, used from the next
+    assg_analyze: "auto", "csr" or "dia"."""
+    _check(lib().assg_set_format(h.ptr, FORMAT[fmt]), h.ptr)
+
+
+def assg_get_format(h: Handle) -> str:
+    """"csr" or "dia": the storage the last analysis chose."""
+    f = C.c_int32()
+    _check(lib().assg_get_format(h.ptr, C.byref(f)), h.ptr)
+    return FORMAT_NAMES[f.value]
 
 
 def _info_dict(info: AssgInfo) -> dict:

@@ -3,6 +3,7 @@
 // every decision is made on the device), timing and result copies.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -233,7 +234,84 @@ CsrView view(assg_handle_t h, const assg_csr_t* A) {
   v.sys_chunk = h->d_chunks + h->nchunk + 1;
   v.nchunk = h->nchunk;
   v.nsys = 1;
+  if (h->fmt == ASSG_FORMAT_DIA) v.dia = h->dia;
   return v;
+}
+
+void refresh_dia(assg_handle_t h, const assg_csr_t* A) {
+  if (h->fmt == ASSG_FORMAT_DIA)
+    launch_dia_fill(h->stream, A->row_ptr, A->col_idx, A->val, A->n, h->dia, h->d_dia);
+}
+
+// Diagonal storage of A (analysis): the offsets of 64 rows spread over the
+// matrix by the golden-ratio sequence (evenly spaced fractions of n land on
+// the boundary planes of power-of-two grids) are the candidates; a kernel
+// then checks that every row's entries lie on them, in order.  Sets h->fmt to ASSG_FORMAT_DIA on success; a
+// matrix that does not fit is an error only when the storage was forced.
+static assg_status_t analyze_dia(assg_handle_t h, const assg_csr_t* A,
+                                 const std::vector<int32_t>& rp) {
+  const bool forced = h->fmt_req == ASSG_FORMAT_DIA;
+  auto no = [&](const std::string& why) {
+    return forced ? fail(h, ASSG_ERR_UNSUPPORTED, "diagonal storage: " + why) : ASSG_OK;
+  };
+  const int64_t n = A->n;
+  std::vector<int64_t> offs;
+  constexpr int NS = 64;
+  std::vector<int32_t> cols;
+  for (int k = 0; k < NS; ++k) {
+    const double f = std::fmod(0.5 + 0.6180339887498949 * k, 1.0);
+    const int64_t i = std::min<int64_t>(n - 1, (int64_t)(f * (double)n));
+    const int32_t e0 = rp[i], e1 = rp[i + 1];
+    if (e1 - e0 > DIA_MAX) return no("a row has more than 32 entries");
+    cols.resize(e1 - e0);
+    if (e1 > e0) {
+      HIP_OR_FAIL(h, hipMemcpyAsync(cols.data(), A->col_idx + e0, (e1 - e0) * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, h->stream));
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    }
+    for (int32_t c : cols) offs.push_back((int64_t)c - i);
+  }
+  std::sort(offs.begin(), offs.end());
+  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+  if (offs.empty() || (int)offs.size() > DIA_MAX) return no("more than 32 diagonals");
+  if (!forced && (double)offs.size() * (double)n > 1.15 * (double)A->nnz)
+    return ASSG_OK;   // too many positions without an entry: CSR reads fewer bytes
+  DiaView D{};
+  D.nd = (int32_t)offs.size();
+  for (int d = 0; d < D.nd; ++d) D.off[d] = (int32_t)offs[d];
+  HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
+  launch_dia_probe(h->stream, A->row_ptr, A->col_idx, n, D, h->d_flag);
+  HIP_OR_FAIL(h, hipGetLastError());
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (h->h_status[0] != 0) return no("an entry lies off the diagonals of the sampled rows");
+  // plain SB_ROWS-row blocks and the reduction chunks over them
+  std::vector<int32_t> blk;
+  for (int64_t r = 0; r < n; r += SB_ROWS) blk.push_back((int32_t)r);
+  blk.push_back((int32_t)n);
+  std::vector<int32_t> cblk, csys, sys_chunk, sys_blk{0, (int32_t)blk.size() - 1};
+  make_chunks(sys_blk, h->gram_blocks[10], cblk, csys, sys_chunk);
+  std::vector<int32_t> tab(blk);
+  tab.insert(tab.end(), cblk.begin(), cblk.end());
+  tab.insert(tab.end(), sys_chunk.begin(), sys_chunk.end());
+  if (hipMalloc(&h->d_dia, (size_t)D.nd * (size_t)n * sizeof(double)) != hipSuccess) {
+    h->d_dia = nullptr;
+    return fail(h, ASSG_ERR_ALLOC, "diagonal storage allocation failed");
+  }
+  HIP_OR_FAIL(h, hipMalloc(&h->d_dia_tab, tab.size() * sizeof(int32_t)));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_dia_tab, tab.data(), tab.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  D.val = h->d_dia;
+  D.blk = h->d_dia_tab;
+  D.nblk = (int32_t)blk.size() - 1;
+  D.cblk = h->d_dia_tab + blk.size();
+  D.nchunk = (int32_t)cblk.size() - 1;
+  D.sys_chunk = D.cblk + cblk.size();
+  h->dia = D;
+  h->fmt = ASSG_FORMAT_DIA;
+  return ASSG_OK;
 }
 
 
@@ -297,7 +375,7 @@ const char* assg_status_string(assg_status_t s) {
     case ASSG_ERR_INVALID_ARG: return "invalid argument";
     case ASSG_ERR_HIP: return "HIP error";
     case ASSG_ERR_ALLOC: return "allocation failed";
-    case ASSG_ERR_UNSUPPORTED: return "unsupported device";
+    case ASSG_ERR_UNSUPPORTED: return "unsupported (device or storage)";
     case ASSG_ERR_NOT_ANALYZED: return "matrix not analyzed";
   }
   return "unknown status";
@@ -407,6 +485,8 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_blke) (void)hipFree(h->d_blke);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_part) (void)hipFree(h->d_part);
+  if (h->d_dia) (void)hipFree(h->d_dia);
+  if (h->d_dia_tab) (void)hipFree(h->d_dia_tab);
   drop_graph(h->g_sstep);
   drop_graph(h->g_hscg);
   if (h->d_forced) (void)hipFree(h->d_forced);
@@ -436,6 +516,12 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   if (h->stream) HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   drop_graph(h->g_sstep);
   drop_graph(h->g_hscg);
+  h->fmt = ASSG_FORMAT_CSR;
+  h->dia = DiaView{};
+  if (h->d_dia) HIP_OR_FAIL(h, hipFree(h->d_dia));
+  if (h->d_dia_tab) HIP_OR_FAIL(h, hipFree(h->d_dia_tab));
+  h->d_dia = nullptr;
+  h->d_dia_tab = nullptr;
   if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
   std::vector<int32_t> rp((size_t)A->n + 1);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
@@ -482,11 +568,30 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   h->d_part = nullptr;
   HIP_OR_FAIL(h, hipMalloc(&h->d_part, reduce_doubles(h->nblk) * sizeof(double)));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));   // host tables above go out of scope
+  if (h->fmt_req != ASSG_FORMAT_CSR) {
+    const assg_status_t st = analyze_dia(h, A, rp);
+    if (st != ASSG_OK) return st;
+  }
   h->an_n = A->n;
   h->an_nnz = A->nnz;
   h->an_rp = A->row_ptr;
   h->an_ci = A->col_idx;
   h->err.clear();
+  return ASSG_OK;
+}
+
+assg_status_t assg_set_format(assg_handle_t h, int32_t format) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (format != ASSG_FORMAT_AUTO && format != ASSG_FORMAT_CSR && format != ASSG_FORMAT_DIA)
+    return fail(h, ASSG_ERR_INVALID_ARG, "format must be AUTO, CSR or DIA");
+  h->fmt_req = format;
+  return ASSG_OK;
+}
+
+assg_status_t assg_get_format(assg_handle_t h, int32_t* format) {
+  if (!h || !format) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  if (h->an_n < 0) return fail(h, ASSG_ERR_NOT_ANALYZED, "no analysis");
+  *format = h->fmt;
   return ASSG_OK;
 }
 
@@ -617,6 +722,7 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
                                   hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
+  refresh_dia(h, A);
   launch_setup(h->stream, h->d_ctl, Av, b, x, pairs, h->d_part);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
@@ -640,7 +746,8 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
                                        reinterpret_cast<const void*>((intptr_t)n),
                                        reinterpret_cast<const void*>((intptr_t)A->nnz),
                                        reinterpret_cast<const void*>((intptr_t)h->nblk),
-                                       reinterpret_cast<const void*>((intptr_t)h->nchunk)};
+                                       reinterpret_cast<const void*>((intptr_t)h->nchunk),
+                                       h->d_dia, h->d_dia_tab};
     st = cached_graph(h, h->g_sstep, key, [&]() {
       for (int r = 0; r < LOOPS_PER_GRAPH; ++r) {
         for (int l = 1; l < sigma; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
@@ -803,6 +910,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_start, h->stream));
+  refresh_dia(h, A);
   launch_h_init(h->stream, h->d_ctl, Av, b, x, r, p, h->d_part);
   HIP_OR_FAIL(h, hipGetLastError());
   if (zero_rhs(h, x, n, info, &st)) return st;
@@ -813,7 +921,8 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
                                      reinterpret_cast<const void*>((intptr_t)n),
                                      reinterpret_cast<const void*>((intptr_t)A->nnz),
                                      reinterpret_cast<const void*>((intptr_t)h->nblk),
-                                     reinterpret_cast<const void*>((intptr_t)h->nchunk)};
+                                     reinterpret_cast<const void*>((intptr_t)h->nchunk),
+                                     h->d_dia, h->d_dia_tab};
   st = cached_graph(h, h->g_hscg, key, [&]() {
     for (int it = 0; it < ITERS_PER_GRAPH; ++it) {
       launch_h_spmv(h->stream, h->d_ctl, Av, p, w, h->d_part);
@@ -885,6 +994,7 @@ assg_status_t assg_basis_gram(assg_handle_t h, const assg_csr_t* A, const double
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+  refresh_dia(h, A);
   launch_pair_init(h->stream, n, p, r, pairs);
   for (int l = 1; l < s; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
   launch_last_gram(h->stream, h->d_ctl, s, Av, pairs, plast, lay.ld, grampart);

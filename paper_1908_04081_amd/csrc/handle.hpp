@@ -40,6 +40,12 @@ struct assg_handle_s {
   int32_t* d_chunks = nullptr;   // chunk starts (nchunk + 1) then system chunk starts (2)
   int32_t nchunk = 0;
   double* d_part = nullptr;      // per-workgroup partial sums (sized at analyze)
+  // storage of A's values for the matrix-powers kernels (assg_set_format)
+  int32_t fmt_req = ASSG_FORMAT_AUTO;
+  int32_t fmt = ASSG_FORMAT_CSR;          // chosen by the last analysis
+  assg::DiaView dia{};                    // nd = 0 unless the diagonal storage was chosen
+  double* d_dia = nullptr;                // nd * n values
+  int32_t* d_dia_tab = nullptr;           // blocks (nblk + 1), chunks (nchunk + 1), {0, nchunk}
   int gram_blocks[assg::MAXS + 1] = {0};   // resident last-sweep workgroups per sigma (chunk count)
   // captured graphs of the single solve's outer loops and of HSCG iterations,
   // valid while the pointers and sizes they were captured with are unchanged
@@ -103,6 +109,9 @@ inline bool overlap(const double* a, const double* b, int64_t n) {
 // Column indices of A inside [0, n), checked on the device (analysis time).
 assg_status_t check_columns(assg_handle_t h, const int32_t* ci, int64_t nnz, int64_t n);
 assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o);
+// Rewrites the diagonal storage from A's CSR values when the analysis chose
+// it (enqueued on the handle's stream; nothing otherwise).
+void refresh_dia(assg_handle_t h, const assg_csr_t* A);
 void init_ctl(assg_handle_t h, Ctl* c, int mode);
 void apply_variant(Ctl* c, const assg_opts_t* o);
 int64_t completed_loops(const Ctl* c);

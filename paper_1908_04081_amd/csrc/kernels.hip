@@ -57,6 +57,49 @@ struct BlockRows {
 };
 
 
+// Row i of A x from the diagonal storage: the products in column order
+// (offsets ascending), each rounded before it is added, as a sequential CSR
+// product adds them; a diagonal position without an entry of A holds 0 and
+// adds +0, which leaves the sum unchanged.  Eight diagonals' loads are
+// issued before their products are added.
+template <int CH, class S>
+__device__ __forceinline__ void dia_row(const DiaView& D, int64_t n, const S& src, int64_t i,
+                                        double& sx, double& sy) {
+#pragma clang fp contract(off)
+  sx = 0.0;
+  sy = 0.0;
+  for (int d0 = 0; d0 < D.nd; d0 += 8) {
+    double v[8];
+    double2 x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int d = d0 + k;
+      const int64_t j = i + D.off[d < DIA_MAX ? d : 0];
+      const bool ok = d < D.nd && j >= 0 && j < n;
+      v[k] = ok ? ldnt(D.val + (int64_t)d * n + i) : 0.0;
+      x[k] = ok ? src.get((int32_t)j) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      sx += v[k] * x[k].x;
+      if constexpr (CH == 2) sy += v[k] * x[k].y;
+    }
+  }
+}
+
+// The row of this thread in a diagonal-storage kernel (one row per thread,
+// blocks of SB_ROWS rows, XCD-aware), or -1.
+__device__ __forceinline__ int64_t dia_thread_row(const CsrView& A) {
+  const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
+  if (bb >= A.dia.nblk) return -1;
+  const int64_t i = (int64_t)A.dia.blk[bb] + threadIdx.x;
+  return i < A.dia.blk[bb + 1] ? i : -1;
+}
+
+static int dia_grid(const CsrView& A) {
+  return (A.dia.nblk + NXCD - 1) / NXCD * NXCD;
+}
+
 // ------------------------------------------------------------------ SpMV
 __global__ __launch_bounds__(256) void k_spmv(CsrView A, const double* __restrict__ x,
                                               double* __restrict__ y) {
@@ -165,10 +208,41 @@ __global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int
   }
 }
 
+// The same level from the diagonal storage (a single system): one row per
+// thread, every load coalesced, no product buffer and no barrier.
+__global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctl, int level,
+                                                   CsrView A, double2* __restrict__ pairs,
+                                                   int64_t ld) {
+  if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
+  const int64_t i = dia_thread_row(A);
+  if (i < 0) return;
+  const double th = ctl->theta[level - 1];
+  const double ga = ctl->gamma[level - 1];
+  const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
+  const double2* __restrict__ X = pairs + (size_t)(level - 1) * ld;
+  const double2* __restrict__ X2 = pairs + (size_t)(level >= 2 ? level - 2 : 0) * ld;
+  double2* __restrict__ Yo = pairs + (size_t)level * ld;
+  const double2 xo = X[i];
+  double2 x2 = make_double2(0.0, 0.0);
+  if (mu != 0.0) x2 = ldnt2(X2 + i);
+  double ax, ay;
+  dia_row<2>(A.dia, A.n, Src2{X}, i, ax, ay);
+  double yx = ax - th * xo.x;
+  double yy = ay - th * xo.y;
+  if (mu != 0.0) {
+    yx -= mu * x2.x;
+    yy -= mu * x2.y;
+  }
+  stnt2(Yo + i, make_double2(yx / ga, yy / ga));
+}
+
 void launch_sweep(hipStream_t s, const Ctl* ctl, int level, const CsrView& A, double2* pairs,
                   int64_t ld) {
-  hipLaunchKernelGGL(k_sweep, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, ctl, level, A,
-                     pairs, ld);
+  if (A.dia.nd > 0)
+    hipLaunchKernelGGL(k_sweep_dia, dim3(dia_grid(A)), dim3(256), 0, s, ctl, level, A, pairs, ld);
+  else
+    hipLaunchKernelGGL(k_sweep, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, ctl, level, A,
+                       pairs, ld);
 }
 
 // --------------------------------- last level fused with the Gram partials
@@ -189,15 +263,26 @@ __device__ double2 g_zero_rows[64];
 // block's nonzeros and row ranges are fetched before the Gram, and its
 // bounds one block earlier still.  At the end the waves' accumulators are
 // added in wave order and the unique entries written as this chunk's
-// partials.
+// partials.  From the diagonal storage (DIA) the products need no LDS, so
+// the tile loads are issued first and stream in while each thread forms its
+// row of A P_{sbar-1}.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-template <int NC, int W>
+template <int NC, int W, bool DIA>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(NC <= 23 ? 3 : 2)))
 void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restrict__ pairs,
                  double* __restrict__ plast, int64_t ld, double* __restrict__ partials) {
   int32_t b0, b1, sys;
-  const int32_t chunk = chunk_of(A, b0, b1, sys);
+  int32_t chunk;
+  if constexpr (DIA) {
+    chunk = xcd_logical(blockIdx.x, gridDim.x);
+    ASSG_DCHECK(chunk >= 0 && chunk < A.dia.nchunk, 14);
+    b0 = A.dia.cblk[chunk];
+    b1 = A.dia.cblk[chunk + 1];
+    sys = 0;
+  } else {
+    chunk = chunk_of(A, b0, b1, sys);
+  }
   const Ctl* ctl = ctls + sys;
   if (ctl->status != ST_RUNNING) return;
   constexpr int NT = 64 * W;
@@ -241,7 +326,7 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   // Row-block bounds come through the scalar cache one block ahead (the
   // partition is read-only), so a block's fetch never waits for them.
   typedef const __attribute__((address_space(4))) int32_t kint;
-  kint* const kblk = (kint*)A.blk;
+  kint* const kblk = (kint*)(DIA ? A.dia.blk : A.blk);
   kint* const kblke = (kint*)A.blke;
   struct Rows {
     int32_t r0, nr, e0, ne, rs, re;
@@ -249,6 +334,12 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   auto bounds = [&](int32_t b, Rows& r) {
     r.r0 = kblk[b];
     r.nr = kblk[b + 1] - r.r0;
+    if constexpr (DIA) {
+      r.e0 = r.ne = 0;
+      ASSG_DCHECK(b >= 0 && b < A.dia.nblk && r.nr >= 1 && r.nr <= TS &&
+                      (int64_t)r.r0 + r.nr <= A.n, 24);
+      return;
+    }
     r.e0 = kblke[b];
     r.ne = kblke[b + 1] - r.e0;
     ASSG_DCHECK(b >= 0 && b < A.nblk, 21);
@@ -258,7 +349,7 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   };
   auto own_range = [&](Rows& r) {   // vector loads, consumed after the next drain
     r.rs = r.re = 0;
-    if (tid < r.nr) {
+    if (!DIA && tid < r.nr) {
       r.rs = A.rp[(int64_t)r.r0 + tid] - r.e0;
       r.re = A.rp[(int64_t)r.r0 + tid + 1] - r.e0;
     }
@@ -272,48 +363,65 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   if (b0 < b1) {
     bounds(b0, cur);
     own_range(cur);
-    if (cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
+    if (!DIA && cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
     if (b0 + 1 < b1) bounds(b0 + 1, nxt);
   }
   for (int32_t b = b0; b < b1; ++b) {
-    // products first (their LDS buffer is the start of the tile), then the
-    // basis pairs into the tile in 64-row loads (levels past sbar and lanes
-    // past the block read zeros); every wave waits for its own before the
-    // barrier, so the tile is complete after it
-    const bool fits = cur.ne <= SB_CAP;
+    // CSR: the products first (their LDS buffer is the start of the tile),
+    // then the block's basis pairs into the tile in 64-row loads; DIA: the
+    // tile loads, then each thread's row of A P_{sbar-1}.  Levels past sbar
+    // and lanes past the block read zeros; 64-row chunks past the block are
+    // not loaded (the Gram stops at the block's last 4-row group, which lies
+    // in a loaded chunk).  Every wave waits for its own loads before the
+    // barrier, so the tile is complete after it.
     const bool own = tid < cur.nr;
     double a = 0.0, unused;
-    if (fits) {
-      if (cur.ne > 0) {
-        double gx[K];
+    if constexpr (DIA) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) gx[k] = xsrc[2 * (int64_t)f.c[k]];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const int32_t e = tid + NT * k;
-          if (e < cur.ne) prod[e] = f.a[k] * gx[k];
+      for (int j = 0; j < NDW; ++j) {
+        const int i = wave + j * W;
+        if ((ND % W == 0 || i < ND) && ((i & 3) << 6) < cur.nr) {
+          const int l = i >> 2, row = ((i & 3) << 6) + lane;
+          const double2* src =
+              (l < s && row < cur.nr) ? pairs + (size_t)l * ld + cur.r0 + row : g_zero_rows + lane;
+          __builtin_amdgcn_global_load_lds(
+              (const void*)src,
+              (void __attribute__((address_space(3)))*)(tile + l * TP + ((i & 3) << 6)), 16, 0,
+              2);   // nt: streamed once
         }
       }
-      __syncthreads();
-      if (own)
-        for (int32_t e = cur.rs; e < cur.re; ++e) a += prod[e];
+      if (own) dia_row<1>(A.dia, A.n, SrcP{xsrc}, (int64_t)cur.r0 + tid, a, unused);
     } else {
-      long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, cur.e0, cur.ne, red, a, unused);
-    }
-    __syncthreads();
+      if (cur.ne <= SB_CAP) {
+        if (cur.ne > 0) {
+          double gx[K];
 #pragma unroll
-    for (int j = 0; j < NDW; ++j) {
-      const int i = wave + j * W;
-      // 64-row chunks past the block are not loaded (the Gram stops at the
-      // block's last 4-row group, which lies in a loaded chunk)
-      if ((ND % W == 0 || i < ND) && ((i & 3) << 6) < cur.nr) {
-        const int l = i >> 2, row = ((i & 3) << 6) + lane;
-        const double2* src =
-            (l < s && row < cur.nr) ? pairs + (size_t)l * ld + cur.r0 + row : g_zero_rows + lane;
-        __builtin_amdgcn_global_load_lds(
-            (const void*)src,
-            (void __attribute__((address_space(3)))*)(tile + l * TP + ((i & 3) << 6)), 16, 0,
-            2);   // nt: streamed once
+          for (int k = 0; k < K; ++k) gx[k] = xsrc[2 * (int64_t)f.c[k]];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int32_t e = tid + NT * k;
+            if (e < cur.ne) prod[e] = f.a[k] * gx[k];
+          }
+        }
+        __syncthreads();
+        if (own)
+          for (int32_t e = cur.rs; e < cur.re; ++e) a += prod[e];
+      } else {
+        long_row<1, NT>(A.ci, A.va, SrcP{xsrc}, cur.e0, cur.ne, red, a, unused);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NDW; ++j) {
+        const int i = wave + j * W;
+        if ((ND % W == 0 || i < ND) && ((i & 3) << 6) < cur.nr) {
+          const int l = i >> 2, row = ((i & 3) << 6) + lane;
+          const double2* src =
+              (l < s && row < cur.nr) ? pairs + (size_t)l * ld + cur.r0 + row : g_zero_rows + lane;
+          __builtin_amdgcn_global_load_lds(
+              (const void*)src,
+              (void __attribute__((address_space(3)))*)(tile + l * TP + ((i & 3) << 6)), 16, 0,
+              2);   // nt: streamed once
+        }
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -334,7 +442,7 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
     if (b + 1 < b1) {
       cur = nxt;
       own_range(cur);
-      if (cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
+      if (!DIA && cur.ne <= SB_CAP && cur.ne > 0) f.issue(A.ci, A.va, cur.e0, cur.ne);
       if (b + 2 < b1) bounds(b + 2, nxt);
     }
     __syncthreads();
@@ -398,7 +506,8 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k)
-    if (at[k] >= 0) partials[(size_t)(tid + k * NT) * A.nchunk + chunk] = sum[k];
+    if (at[k] >= 0)
+      partials[(size_t)(tid + k * NT) * (DIA ? A.dia.nchunk : A.nchunk) + chunk] = sum[k];
 }
 
 template <int NC>
@@ -408,7 +517,7 @@ template <int NC>
 static int last_gram_blocks_nc(int cus) {
   constexpr int W = gram_waves<NC>();
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_last_gram<NC, W>, 64 * W, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_last_gram<NC, W, false>, 64 * W, 0) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -447,8 +556,12 @@ void launch_last_gram(hipStream_t s, const Ctl* ctl, int sigma, const CsrView& A
                       const double2* pairs, double* plast, int64_t ld, double* partials) {
   ASSG_SIGMA_SWITCH(sigma, {
     constexpr int W = gram_waves<NC>();
-    hipLaunchKernelGGL((k_last_gram<NC, W>), dim3(A.nchunk), dim3(64 * W), 0, s, ctl, A, pairs,
-                       plast, ld, partials);
+    if (A.dia.nd > 0)
+      hipLaunchKernelGGL((k_last_gram<NC, W, true>), dim3(A.dia.nchunk), dim3(64 * W), 0, s, ctl,
+                         A, pairs, plast, ld, partials);
+    else
+      hipLaunchKernelGGL((k_last_gram<NC, W, false>), dim3(A.nchunk), dim3(64 * W), 0, s, ctl, A,
+                         pairs, plast, ld, partials);
   });
 }
 
@@ -480,8 +593,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(Ctl* __restrict__ ctls, Csr
 
 void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, const CsrView& A,
                         const double* partials) {
-  ASSG_SIGMA_SWITCH(sigma, hipLaunchKernelGGL(k_gram_reduce<NC>, dim3(NC * (NC + 1) / 2, A.nsys),
-                                              dim3(256), 0, s, ctl, A, partials));
+  // the partials are laid out over the chunks of the storage the last sweep read
+  CsrView v = A;
+  if (A.dia.nd > 0) {
+    v.nchunk = A.dia.nchunk;
+    v.cblk = A.dia.cblk;
+    v.sys_chunk = A.dia.sys_chunk;
+  }
+  ASSG_SIGMA_SWITCH(sigma, hipLaunchKernelGGL(k_gram_reduce<NC>, dim3(NC * (NC + 1) / 2, v.nsys),
+                                              dim3(256), 0, s, ctl, v, partials));
 }
 
 // -------------------------------------------------------------- recovery
@@ -718,8 +838,34 @@ __global__ __launch_bounds__(1024) void k_fin_alpha(Ctl* ctl, const double* __re
   }
 }
 
+// w = A p and the p^T w partials from the diagonal storage.
+__global__ __launch_bounds__(256) void k_h_spmv_dia(const Ctl* ctl, CsrView A,
+                                                    const double* __restrict__ p,
+                                                    double* __restrict__ w,
+                                                    double* __restrict__ part) {
+  if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
+  __shared__ double red[4];
+  const int64_t i = dia_thread_row(A);
+  double my = 0.0;
+  if (i >= 0) {
+    const double pi = p[i];
+    double v, unused;
+    dia_row<1>(A.dia, A.n, Src1{p}, i, v, unused);
+    stnt(w + i, v);
+    my = pi * v;
+  }
+  my = block_sum<256>(my, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = my;
+}
+
 void launch_h_spmv(hipStream_t s, Ctl* ctl, const CsrView& A, const double* p, double* w,
                    double* part) {
+  if (A.dia.nd > 0) {
+    const int g = dia_grid(A);
+    hipLaunchKernelGGL(k_h_spmv_dia, dim3(g), dim3(256), 0, s, ctl, A, p, w, part);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctl, part, g);
+    return;
+  }
   const int g = block_grid(A, 1 << 30);
   hipLaunchKernelGGL(k_h_spmv, dim3(g), dim3(256), 0, s, ctl, A, p, w, part);
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctl, part, g);
@@ -831,6 +977,81 @@ void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, cons
                           double alpha, double* out) {
   hipLaunchKernelGGL(k_outer_pattern, dim3(block_grid(A, 1 << 30)), dim3(256), 0, s, A, u, v,
                      alpha, out);
+}
+
+// ---------------------------------------------------- diagonal storage
+// *flag = 1 (every offending thread stores the same value) unless each
+// row's column offsets c - i are a strictly increasing subsequence of the
+// ascending D.off (sorted, duplicate-free rows whose entries all lie on the
+// diagonals).
+__global__ __launch_bounds__(256) void k_dia_probe(const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, int64_t n,
+                                                   DiaView D, int32_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n && !bad;
+       i += (int64_t)gridDim.x * 256) {
+    int d = 0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int64_t off = (int64_t)ci[e] - i;
+      while (d < D.nd && D.off[d] < off) ++d;
+      if (d >= D.nd || D.off[d] != off) {
+        bad = true;
+        break;
+      }
+      ++d;
+    }
+  }
+  if (bad) flag[0] = 1;
+}
+
+void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, int64_t n,
+                      const DiaView& D, int32_t* flag) {
+  const int64_t g = (n + 255) / 256;
+  if (g > 0)
+    hipLaunchKernelGGL(k_dia_probe, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, rp,
+                       ci, n, D, flag);
+}
+
+// val[d * n + i] = A[i][i + off[d]], or 0.  One workgroup per 64 rows:
+// their CSR entries (at most 32 per row, which the probe has checked) come
+// into the LDS in coalesced loads, then four threads per row walk the row's
+// entries against the diagonals in order, each writing every fourth
+// diagonal (sixteen consecutive rows per wave and diagonal).
+__global__ __launch_bounds__(256) void k_dia_fill(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ va, int64_t n,
+                                                  DiaView D, double* __restrict__ val) {
+  constexpr int RB = 64;
+  __shared__ int32_t sc[RB * DIA_MAX];
+  __shared__ double sv[RB * DIA_MAX];
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  if (r0 >= n) return;
+  const int64_t r1 = r0 + RB < n ? r0 + RB : n;
+  const int32_t e0 = rp[r0];
+  const int32_t ne = rp[r1] - e0;
+  ASSG_DCHECK(ne >= 0 && ne <= RB * DIA_MAX, 41);
+  for (int32_t e = threadIdx.x; e < ne; e += 256) {
+    sc[e] = ldnt(ci + e0 + e);
+    sv[e] = ldnt(va + e0 + e);
+  }
+  __syncthreads();
+  const int q = threadIdx.x & 3;
+  const int64_t i = r0 + (threadIdx.x >> 2);
+  if (i >= r1) return;
+  int32_t e = rp[i] - e0;
+  const int32_t e1 = rp[i + 1] - e0;
+  for (int d = 0; d < D.nd; ++d) {
+    double v = 0.0;
+    if (e < e1 && (int64_t)sc[e] - i == D.off[d]) v = sv[e++];
+    if ((d & 3) == q) stnt(val + (int64_t)d * n + i, v);
+  }
+}
+
+void launch_dia_fill(hipStream_t s, const int32_t* rp, const int32_t* ci, const double* va,
+                     int64_t n, const DiaView& D, double* val) {
+  const int64_t g = (n + 63) / 64;
+  if (g > 0)
+    hipLaunchKernelGGL(k_dia_fill, dim3((unsigned)g), dim3(256), 0, s, rp, ci, va, n, D, val);
 }
 
 // *flag = 1 when a column index of ci[0, nnz) lies outside [0, n) (every

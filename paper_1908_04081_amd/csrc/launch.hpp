@@ -12,6 +12,25 @@
 
 namespace assg {
 
+// Diagonal storage of a single system whose nonzeros all lie on at most
+// DIA_MAX diagonals (stencil matrices): val[d * n + i] = A[i][i + off[d]],
+// 0 where A has no entry, offsets ascending, so a row's products are added
+// in column order as in the CSR kernels, and no column index or row pointer
+// is read.  Its row kernels take plain blocks of SB_ROWS rows (blk) and its
+// reduction chunks run over those blocks (cblk, sys_chunk).  nd = 0: the
+// matrix is read as CSR.
+constexpr int DIA_MAX = 32;
+struct DiaView {
+  int32_t nd;
+  int32_t off[DIA_MAX];
+  const double* val;
+  const int32_t* blk;        // nblk + 1 row starts
+  int32_t nblk;
+  const int32_t* cblk;       // nchunk + 1 first blocks
+  const int32_t* sys_chunk;  // {0, nchunk}
+  int32_t nchunk;
+};
+
 // A matrix with its row-block partition.  A batch of independent systems
 // is one block-diagonal matrix (systems' rows and columns concatenated);
 // row blocks never straddle systems, and neither do the "chunks" (runs of
@@ -31,6 +50,7 @@ struct CsrView {
   const int32_t* sys_chunk;  // nsys + 1: first chunk of each system
   int32_t nchunk;            // a multiple of 8 (trailing chunks may be empty)
   int32_t nsys;
+  DiaView dia;               // diagonal storage of a single system (dia.nd = 0: none)
 };
 
 void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
@@ -81,6 +101,15 @@ void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, doubl
 // out[k] = alpha u[row(k)] v[col(k)] on A's pattern.
 void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
                           double alpha, double* out);
+
+// Diagonal storage: *flag = 1 unless every row's column offsets form a
+// strictly increasing subsequence of D.off (flag cleared by the caller);
+// the fill writes D's values (every position, 0 where A has no entry) from
+// the CSR values.
+void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, int64_t n,
+                      const DiaView& D, int32_t* flag);
+void launch_dia_fill(hipStream_t s, const int32_t* rp, const int32_t* ci, const double* va,
+                     int64_t n, const DiaView& D, double* val);
 
 // *flag = 1 if some ci[e], e < nnz, is outside [0, n) (flag cleared by the caller).
 void launch_check_cols(hipStream_t s, const int32_t* ci, int64_t nnz, int32_t n, int32_t* flag);
