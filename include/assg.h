@@ -236,7 +236,8 @@ assg_status_t assg_workspace_size(int64_t n, int32_t s_max, size_t* bytes);
 assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
 
 /* Storage the matrix-powers kernels read A from, chosen by the next
- * assg_analyze of a single system (batches always read CSR):
+ * assg_analyze or assg_batch_analyze (a batch takes the diagonal storage
+ * only when every system fits it, each system with its own diagonals):
  *  - ASSG_FORMAT_AUTO (the default): diagonal storage when every entry of A
  *    lies on one of at most 32 diagonals (i, i + off) and those diagonals
  *    hold at most 15% more positions than A has entries (stencil matrices),
@@ -244,7 +245,7 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A);
  *  - ASSG_FORMAT_CSR: CSR always;
  *  - ASSG_FORMAT_DIA: diagonal storage whatever its fill, or
  *    ASSG_ERR_UNSUPPORTED from the analysis when some entry lies off 32
- *    diagonals (the handle is then left with no analysis).
+ *    diagonals (the handle is then left with no analysis of that kind).
  * The diagonal storage is the library's copy of A's values, n per diagonal
  * (0 where A has no entry), allocated at analysis and refreshed from the CSR
  * values at the start of every solve and assg_basis_gram call, so values
@@ -265,6 +266,10 @@ assg_status_t assg_set_format(assg_handle_t h, int32_t format);
 /* The storage the last successful analysis chose (ASSG_FORMAT_CSR or
  * ASSG_FORMAT_DIA); ASSG_ERR_NOT_ANALYZED when there is none. */
 assg_status_t assg_get_format(assg_handle_t h, int32_t* format);
+
+/* The storage the last batch analysis chose; ASSG_ERR_NOT_ANALYZED when
+ * there is none. */
+assg_status_t assg_batch_format(assg_handle_t h, int32_t* format);
 
 /* ------------------------------------------------------------- the solves */
 

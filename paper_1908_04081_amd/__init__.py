@@ -135,6 +135,7 @@ def load(path: str = LIB_PATH):
         "assg_analyze": (I32, [P, C.POINTER(AssgCsr)]),
         "assg_set_format": (I32, [P, I32]),
         "assg_get_format": (I32, [P, C.POINTER(I32)]),
+        "assg_batch_format": (I32, [P, C.POINTER(I32)]),
         "assg_solve": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts), P, C.c_size_t,
                              C.POINTER(AssgInfo)]),
         "assg_solve_noalloc": (I32, [P, C.POINTER(AssgCsr), P, P, C.POINTER(AssgOpts),
@@ -326,6 +327,13 @@ def assg_get_format(h: Handle) -> str:
     """"csr" or "dia": the storage the last analysis chose."""
     f = C.c_int32()
     _check(lib().assg_get_format(h.ptr, C.byref(f)), h.ptr)
+    return FORMAT_NAMES[f.value]
+
+
+def assg_batch_format(h: Handle) -> str:
+    """"csr" or "dia": the storage the last batch analysis chose."""
+    f = C.c_int32()
+    _check(lib().assg_batch_format(h.ptr, C.byref(f)), h.ptr)
     return FORMAT_NAMES[f.value]
 
 

@@ -234,26 +234,22 @@ CsrView view(assg_handle_t h, const assg_csr_t* A) {
   v.sys_chunk = h->d_chunks + h->nchunk + 1;
   v.nchunk = h->nchunk;
   v.nsys = 1;
-  if (h->fmt == ASSG_FORMAT_DIA) v.dia = h->dia;
+  if (h->fmt == ASSG_FORMAT_DIA) v.dia = h->dia.view;
   return v;
 }
 
 void refresh_dia(assg_handle_t h, const assg_csr_t* A) {
   if (h->fmt == ASSG_FORMAT_DIA)
-    launch_dia_fill(h->stream, A->row_ptr, A->col_idx, A->val, A->n, h->dia, h->d_dia);
+    launch_dia_fill(h->stream, A->row_ptr, A->col_idx, A->val, h->dia.rec[0], h->dia.val);
 }
 
-// Diagonal storage of A (analysis): the offsets of 64 rows spread over the
-// matrix by the golden-ratio sequence (evenly spaced fractions of n land on
-// the boundary planes of power-of-two grids) are the candidates; a kernel
-// then checks that every row's entries lie on them, in order.  Sets h->fmt to ASSG_FORMAT_DIA on success; a
-// matrix that does not fit is an error only when the storage was forced.
-static assg_status_t analyze_dia(assg_handle_t h, const assg_csr_t* A,
-                                 const std::vector<int32_t>& rp) {
-  const bool forced = h->fmt_req == ASSG_FORMAT_DIA;
-  auto no = [&](const std::string& why) {
-    return forced ? fail(h, ASSG_ERR_UNSUPPORTED, "diagonal storage: " + why) : ASSG_OK;
-  };
+// The offsets of 64 rows spread over the matrix by the golden-ratio
+// sequence (evenly spaced fractions of n land on the boundary planes of
+// power-of-two grids and miss diagonals) are the candidates; a kernel then
+// checks that every row's entries lie on them, in order.
+assg_status_t dia_detect(assg_handle_t h, const assg_csr_t* A, const int32_t* rp, bool check_fill,
+                         DiaSys* R, bool* fits, std::string* why) {
+  *fits = false;
   const int64_t n = A->n;
   std::vector<int64_t> offs;
   constexpr int NS = 64;
@@ -262,7 +258,10 @@ static assg_status_t analyze_dia(assg_handle_t h, const assg_csr_t* A,
     const double f = std::fmod(0.5 + 0.6180339887498949 * k, 1.0);
     const int64_t i = std::min<int64_t>(n - 1, (int64_t)(f * (double)n));
     const int32_t e0 = rp[i], e1 = rp[i + 1];
-    if (e1 - e0 > DIA_MAX) return no("a row has more than 32 entries");
+    if (e1 - e0 > DIA_MAX) {
+      *why = "a row has more than 32 entries";
+      return ASSG_OK;
+    }
     cols.resize(e1 - e0);
     if (e1 > e0) {
       HIP_OR_FAIL(h, hipMemcpyAsync(cols.data(), A->col_idx + e0, (e1 - e0) * sizeof(int32_t),
@@ -273,43 +272,108 @@ static assg_status_t analyze_dia(assg_handle_t h, const assg_csr_t* A,
   }
   std::sort(offs.begin(), offs.end());
   offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
-  if (offs.empty() || (int)offs.size() > DIA_MAX) return no("more than 32 diagonals");
-  if (!forced && (double)offs.size() * (double)n > 1.15 * (double)A->nnz)
-    return ASSG_OK;   // too many positions without an entry: CSR reads fewer bytes
-  DiaView D{};
-  D.nd = (int32_t)offs.size();
-  for (int d = 0; d < D.nd; ++d) D.off[d] = (int32_t)offs[d];
+  if (offs.empty() || (int)offs.size() > DIA_MAX) {
+    *why = "more than 32 diagonals";
+    return ASSG_OK;
+  }
+  if (check_fill && (double)offs.size() * (double)n > 1.15 * (double)A->nnz) {
+    *why = "the diagonals hold more than 15% more positions than A has entries";
+    return ASSG_OK;
+  }
+  *R = DiaSys{};
+  R->n = (int32_t)n;
+  R->nd = (int32_t)offs.size();
+  for (int d = 0; d < R->nd; ++d) R->off[d] = (int32_t)offs[d];
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, sizeof(int32_t), h->stream));
-  launch_dia_probe(h->stream, A->row_ptr, A->col_idx, n, D, h->d_flag);
+  launch_dia_probe(h->stream, A->row_ptr, A->col_idx, *R, h->d_flag);
   HIP_OR_FAIL(h, hipGetLastError());
   HIP_OR_FAIL(h, hipMemcpyAsync(h->h_status, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
                                 h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  if (h->h_status[0] != 0) return no("an entry lies off the diagonals of the sampled rows");
-  // plain SB_ROWS-row blocks and the reduction chunks over them
-  std::vector<int32_t> blk;
-  for (int64_t r = 0; r < n; r += SB_ROWS) blk.push_back((int32_t)r);
-  blk.push_back((int32_t)n);
-  std::vector<int32_t> cblk, csys, sys_chunk, sys_blk{0, (int32_t)blk.size() - 1};
-  make_chunks(sys_blk, h->gram_blocks[10], cblk, csys, sys_chunk);
-  std::vector<int32_t> tab(blk);
-  tab.insert(tab.end(), cblk.begin(), cblk.end());
-  tab.insert(tab.end(), sys_chunk.begin(), sys_chunk.end());
-  if (hipMalloc(&h->d_dia, (size_t)D.nd * (size_t)n * sizeof(double)) != hipSuccess) {
-    h->d_dia = nullptr;
-    return fail(h, ASSG_ERR_ALLOC, "diagonal storage allocation failed");
+  if (h->h_status[0] != 0) {
+    *why = "an entry lies off the diagonals of the sampled rows";
+    return ASSG_OK;
   }
-  HIP_OR_FAIL(h, hipMalloc(&h->d_dia_tab, tab.size() * sizeof(int32_t)));
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_dia_tab, tab.data(), tab.size() * sizeof(int32_t),
+  *fits = true;
+  return ASSG_OK;
+}
+
+void dia_release(DiaStore* S) {
+  for (void* p : {(void*)S->val, (void*)S->sys, (void*)S->tab})
+    if (p) (void)hipFree(p);
+  *S = DiaStore{};
+}
+
+assg_status_t dia_build(assg_handle_t h, std::vector<DiaSys>& R, int chunk_target, DiaStore* S) {
+  dia_release(S);
+  const int nsys = (int)R.size();
+  std::vector<int32_t> blk, bsys, sys_blk{0};
+  int64_t nval = 0;
+  int32_t ndmax = 0;
+  for (int i = 0; i < nsys; ++i) {
+    R[i].val0 = nval;
+    nval += (int64_t)R[i].nd * R[i].n;
+    ndmax = std::max(ndmax, R[i].nd);
+    for (int64_t r = 0; r < R[i].n; r += SB_ROWS) {
+      blk.push_back((int32_t)(R[i].row0 + r));
+      bsys.push_back(i);
+    }
+    sys_blk.push_back((int32_t)blk.size());
+  }
+  blk.push_back((int32_t)(R[nsys - 1].row0 + R[nsys - 1].n));
+  std::vector<int32_t> cblk, csys, sys_chunk;
+  make_chunks(sys_blk, chunk_target, cblk, csys, sys_chunk);
+  std::vector<int32_t> tab(blk);
+  tab.insert(tab.end(), bsys.begin(), bsys.end());
+  tab.insert(tab.end(), cblk.begin(), cblk.end());
+  tab.insert(tab.end(), csys.begin(), csys.end());
+  tab.insert(tab.end(), sys_chunk.begin(), sys_chunk.end());
+  if (hipMalloc(&S->val, (size_t)nval * sizeof(double)) != hipSuccess) {
+    S->val = nullptr;
+    (void)hipGetLastError();
+    return ASSG_ERR_ALLOC;
+  }
+  HIP_OR_FAIL(h, hipMalloc(&S->sys, (size_t)nsys * sizeof(DiaSys)));
+  HIP_OR_FAIL(h, hipMalloc(&S->tab, tab.size() * sizeof(int32_t)));
+  HIP_OR_FAIL(h, hipMemcpyAsync(S->sys, R.data(), (size_t)nsys * sizeof(DiaSys),
                                 hipMemcpyHostToDevice, h->stream));
-  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  D.val = h->d_dia;
-  D.blk = h->d_dia_tab;
-  D.nblk = (int32_t)blk.size() - 1;
-  D.cblk = h->d_dia_tab + blk.size();
+  HIP_OR_FAIL(h, hipMemcpyAsync(S->tab, tab.data(), tab.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));   // the host tables go out of scope
+  DiaView& D = S->view;
+  D = DiaView{};
+  D.nd = ndmax;
+  D.sys = S->sys;
+  D.val = S->val;
+  D.nblk = (int32_t)bsys.size();
+  D.blk = S->tab;
+  D.bsys = nsys > 1 ? S->tab + blk.size() : nullptr;
   D.nchunk = (int32_t)cblk.size() - 1;
-  D.sys_chunk = D.cblk + cblk.size();
-  h->dia = D;
+  D.cblk = S->tab + blk.size() + bsys.size();
+  D.csys = nsys > 1 ? D.cblk + cblk.size() : nullptr;
+  D.sys_chunk = D.cblk + cblk.size() + csys.size();
+  S->rec = R;
+  return ASSG_OK;
+}
+
+// Diagonal storage of a single system at analysis: sets h->fmt to
+// ASSG_FORMAT_DIA when A fits it; a matrix that does not fit is an error
+// only when the storage was forced.
+static assg_status_t analyze_dia(assg_handle_t h, const assg_csr_t* A,
+                                 const std::vector<int32_t>& rp) {
+  const bool forced = h->fmt_req == ASSG_FORMAT_DIA;
+  std::vector<DiaSys> R(1);
+  bool fits = false;
+  std::string why;
+  assg_status_t st = dia_detect(h, A, rp.data(), !forced, &R[0], &fits, &why);
+  if (st != ASSG_OK) return st;
+  if (!fits) return forced ? fail(h, ASSG_ERR_UNSUPPORTED, "diagonal storage: " + why) : ASSG_OK;
+  st = dia_build(h, R, h->gram_blocks[10], &h->dia);
+  if (st == ASSG_ERR_ALLOC) {   // AUTO falls back to CSR
+    dia_release(&h->dia);
+    return forced ? fail(h, ASSG_ERR_ALLOC, "diagonal storage allocation failed") : ASSG_OK;
+  }
+  if (st != ASSG_OK) return st;
   h->fmt = ASSG_FORMAT_DIA;
   return ASSG_OK;
 }
@@ -485,8 +549,7 @@ assg_status_t assg_destroy(assg_handle_t h) {
   if (h->d_blke) (void)hipFree(h->d_blke);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_part) (void)hipFree(h->d_part);
-  if (h->d_dia) (void)hipFree(h->d_dia);
-  if (h->d_dia_tab) (void)hipFree(h->d_dia_tab);
+  dia_release(&h->dia);
   drop_graph(h->g_sstep);
   drop_graph(h->g_hscg);
   if (h->d_forced) (void)hipFree(h->d_forced);
@@ -517,11 +580,7 @@ assg_status_t assg_analyze(assg_handle_t h, const assg_csr_t* A) {
   drop_graph(h->g_sstep);
   drop_graph(h->g_hscg);
   h->fmt = ASSG_FORMAT_CSR;
-  h->dia = DiaView{};
-  if (h->d_dia) HIP_OR_FAIL(h, hipFree(h->d_dia));
-  if (h->d_dia_tab) HIP_OR_FAIL(h, hipFree(h->d_dia_tab));
-  h->d_dia = nullptr;
-  h->d_dia_tab = nullptr;
+  dia_release(&h->dia);
   if (!csr_ok(A)) return fail(h, ASSG_ERR_INVALID_ARG, "invalid CSR descriptor");
   std::vector<int32_t> rp((size_t)A->n + 1);
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
@@ -747,7 +806,7 @@ static assg_status_t solve_impl(assg_handle_t h, const assg_csr_t* A, const doub
                                        reinterpret_cast<const void*>((intptr_t)A->nnz),
                                        reinterpret_cast<const void*>((intptr_t)h->nblk),
                                        reinterpret_cast<const void*>((intptr_t)h->nchunk),
-                                       h->d_dia, h->d_dia_tab};
+                                       h->dia.val, h->dia.tab};
     st = cached_graph(h, h->g_sstep, key, [&]() {
       for (int r = 0; r < LOOPS_PER_GRAPH; ++r) {
         for (int l = 1; l < sigma; ++l) launch_sweep(h->stream, h->d_ctl, l, Av, pairs, lay.ld);
@@ -922,7 +981,7 @@ assg_status_t assg_hscg_solve(assg_handle_t h, const assg_csr_t* A, const double
                                      reinterpret_cast<const void*>((intptr_t)A->nnz),
                                      reinterpret_cast<const void*>((intptr_t)h->nblk),
                                      reinterpret_cast<const void*>((intptr_t)h->nchunk),
-                                     h->d_dia, h->d_dia_tab};
+                                     h->dia.val, h->dia.tab};
   st = cached_graph(h, h->g_hscg, key, [&]() {
     for (int it = 0; it < ITERS_PER_GRAPH; ++it) {
       launch_h_spmv(h->stream, h->d_ctl, Av, p, w, h->d_part);

@@ -36,6 +36,7 @@ CsrView batch_view(assg_handle_t h) {
   v.sys_chunk = B.chunks + 2 * B.nchunk + 1;
   v.nchunk = B.nchunk;
   v.nsys = B.nsys;
+  if (B.fmt == ASSG_FORMAT_DIA) v.dia = B.dia.view;
   return v;
 }
 
@@ -90,6 +91,7 @@ void batch_release(assg_handle_t h) {
     if (p) (void)hipFree(p);
   for (void* p : {(void*)B.hctl, (void*)B.hstat, (void*)B.hnb})
     if (p) (void)hipHostFree(p);
+  dia_release(&B.dia);
   B = assg_handle_s::Batch();
 }
 
@@ -267,11 +269,56 @@ assg_status_t assg_batch_analyze(assg_handle_t h, int32_t nsys, const assg_csr_t
                                 hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMalloc(&B.part, reduce_doubles(B.nblk) * sizeof(double)));
   HIP_OR_FAIL(h, hipMalloc(&B.dctl, (size_t)nsys * sizeof(Ctl)));
+  // the diagonal storage when every system fits it (assg_set_format; a
+  // batch is read in one storage)
+  B.fmt = ASSG_FORMAT_CSR;
+  if (h->fmt_req != ASSG_FORMAT_CSR) {
+    const bool forced = h->fmt_req == ASSG_FORMAT_DIA;
+    std::vector<DiaSys> R(nsys);
+    bool all = true;
+    std::string why;
+    for (int i = 0; i < nsys && all; ++i) {
+      const assg_status_t st = dia_detect(h, &A[i], rps[i].data(), !forced, &R[i], &all, &why);
+      if (st != ASSG_OK) return st;
+      R[i].row0 = row0[i];
+      if (!all) why = "system " + std::to_string(i) + ": " + why;
+    }
+    if (!all && forced) {
+      batch_release(h);
+      return fail(h, ASSG_ERR_UNSUPPORTED, "diagonal storage: " + why);
+    }
+    if (all) {
+      const assg_status_t st = dia_build(h, R, h->gram_blocks[10], &B.dia);
+      if (st == ASSG_ERR_ALLOC && forced) {
+        batch_release(h);
+        return fail(h, ASSG_ERR_ALLOC, "diagonal storage allocation failed");
+      }
+      if (st == ASSG_OK && B.dia.view.nchunk > 4096) {
+        dia_release(&B.dia);
+        if (forced) {
+          batch_release(h);
+          return fail(h, ASSG_ERR_INVALID_ARG, "too many systems for the reduction chunks");
+        }
+      } else if (st == ASSG_OK) {
+        B.fmt = ASSG_FORMAT_DIA;
+      } else if (st != ASSG_ERR_ALLOC) {
+        return st;
+      }
+    }
+  }
   HIP_OR_FAIL(h, hipHostMalloc(&B.hctl, (size_t)nsys * sizeof(Ctl), hipHostMallocDefault));
   HIP_OR_FAIL(h, hipHostMalloc(&B.hstat, (size_t)nsys * sizeof(int32_t), hipHostMallocDefault));
   HIP_OR_FAIL(h, hipHostMalloc(&B.hnb, (size_t)nsys * sizeof(double), hipHostMallocDefault));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));   // host tables above go out of scope
   h->err.clear();
+  return ASSG_OK;
+}
+
+assg_status_t assg_batch_format(assg_handle_t h, int32_t* format) {
+  if (!h) return ASSG_ERR_INVALID_ARG;
+  if (!format) return fail(h, ASSG_ERR_INVALID_ARG, "null argument");
+  if (h->bat.nsys < 1) return fail(h, ASSG_ERR_NOT_ANALYZED, "no batch analyzed");
+  *format = h->bat.fmt;
   return ASSG_OK;
 }
 
@@ -335,6 +382,9 @@ assg_status_t assg_batch_solve(assg_handle_t h, int32_t nsys, const assg_csr_t* 
   HIP_OR_FAIL(h, hipEventRecord(h->ev_in, h->user_stream));
   HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->ev_in, 0));
   for (int i = 0; i < nsys; ++i) {
+    if (B.fmt == ASSG_FORMAT_DIA)
+      launch_dia_fill(h->stream, A[i].row_ptr, A[i].col_idx, A[i].val, B.dia.rec[i],
+                      B.dia.val + B.dia.rec[i].val0);
     HIP_OR_FAIL(h, hipMemcpyAsync(B.vac + B.nz0[i], A[i].val, (size_t)B.nnz[i] * sizeof(double),
                                   hipMemcpyDeviceToDevice, h->stream));
     HIP_OR_FAIL(h, hipMemcpyAsync(B.b + B.row0[i], b[i], (size_t)B.n[i] * sizeof(double),

@@ -11,6 +11,17 @@
 #include "ctl.hpp"
 #include "launch.hpp"
 
+// Diagonal storage of an analysis (single system or batch): the kernels'
+// view, the systems' records (host copy, for the refills) and the device
+// buffers.
+struct DiaStore {
+  assg::DiaView view{};                // view.nd = 0: not in use
+  std::vector<assg::DiaSys> rec;
+  double* val = nullptr;
+  assg::DiaSys* sys = nullptr;
+  int32_t* tab = nullptr;              // blk, bsys, cblk, csys, sys_chunk
+};
+
 // The state behind an assg_handle_t.
 struct assg_handle_s {
   int device = 0;
@@ -43,9 +54,7 @@ struct assg_handle_s {
   // storage of A's values for the matrix-powers kernels (assg_set_format)
   int32_t fmt_req = ASSG_FORMAT_AUTO;
   int32_t fmt = ASSG_FORMAT_CSR;          // chosen by the last analysis
-  assg::DiaView dia{};                    // nd = 0 unless the diagonal storage was chosen
-  double* d_dia = nullptr;                // nd * n values
-  int32_t* d_dia_tab = nullptr;           // blocks (nblk + 1), chunks (nchunk + 1), {0, nchunk}
+  DiaStore dia;                           // in use when fmt is ASSG_FORMAT_DIA
   int gram_blocks[assg::MAXS + 1] = {0};   // resident last-sweep workgroups per sigma (chunk count)
   // captured graphs of the single solve's outer loops and of HSCG iterations,
   // valid while the pointers and sizes they were captured with are unchanged
@@ -74,6 +83,9 @@ struct assg_handle_s {
     assg_tune_class_t tune[ASSG_TUNE_CLASSES] = {};        // the tuner's choice per size class
     hipGraphExec_t graph = nullptr;            // captured outer loops
     int graph_sigma = 0;
+    int32_t fmt = ASSG_FORMAT_CSR;             // storage the batch analysis chose
+    DiaStore dia;
+    std::vector<const int32_t*> ci;            // the caller's column indices (refills)
   } bat;
   double leja[assg::MAXS];
   std::string err;
@@ -109,9 +121,22 @@ inline bool overlap(const double* a, const double* b, int64_t n) {
 // Column indices of A inside [0, n), checked on the device (analysis time).
 assg_status_t check_columns(assg_handle_t h, const int32_t* ci, int64_t nnz, int64_t n);
 assg_status_t validate_opts(assg_handle_t h, const assg_opts_t* o);
-// Rewrites the diagonal storage from A's CSR values when the analysis chose
-// it (enqueued on the handle's stream; nothing otherwise).
+// Rewrites the single analysis's diagonal storage from A's CSR values when
+// it chose that storage (enqueued on the handle's stream; nothing otherwise).
 void refresh_dia(assg_handle_t h, const assg_csr_t* A);
+// Diagonal storage of one system: the offsets of 64 sampled rows (rp: its
+// row pointers on the host), checked on every row on the device.  *fits is
+// false (why set) when an entry lies off at most DIA_MAX diagonals, or, with
+// check_fill, when the diagonals hold more than 15% more positions than A
+// has entries; R gets n, nd and the offsets.
+assg_status_t dia_detect(assg_handle_t h, const assg_csr_t* A, const int32_t* rp, bool check_fill,
+                         DiaSys* R, bool* fits, std::string* why);
+// Allocates the storage of the systems in R (their val0 set here; row0 and
+// row counts as given) with blocks of at most SB_ROWS rows per system and
+// reduction chunks over them; an allocation failure leaves S empty and
+// returns ASSG_ERR_ALLOC.
+assg_status_t dia_build(assg_handle_t h, std::vector<DiaSys>& R, int chunk_target, DiaStore* S);
+void dia_release(DiaStore* S);
 void init_ctl(assg_handle_t h, Ctl* c, int mode);
 void apply_variant(Ctl* c, const assg_opts_t* o);
 int64_t completed_loops(const Ctl* c);

@@ -57,27 +57,31 @@ struct BlockRows {
 };
 
 
-// Row i of A x from the diagonal storage: the products in column order
-// (offsets ascending), each rounded before it is added, as a sequential CSR
-// product adds them; a diagonal position without an entry of A holds 0 and
-// adds +0, which leaves the sum unchanged.  Eight diagonals' loads are
-// issued before their products are added.
+// Local row i of system R's part of A x from the diagonal storage: the
+// products in column order (offsets ascending), each rounded before it is
+// added, as a sequential CSR product adds them; a diagonal position without
+// an entry of A holds 0 and adds +0, which leaves the sum unchanged.  Eight
+// diagonals' loads are issued before their products are added.  src is
+// indexed by the batch row (R.row0 + column).
 template <int CH, class S>
-__device__ __forceinline__ void dia_row(const DiaView& D, int64_t n, const S& src, int64_t i,
-                                        double& sx, double& sy) {
+__device__ __forceinline__ void dia_row(const DiaSys& R, const double* __restrict__ val,
+                                        const S& src, int64_t i, double& sx, double& sy) {
 #pragma clang fp contract(off)
   sx = 0.0;
   sy = 0.0;
-  for (int d0 = 0; d0 < D.nd; d0 += 8) {
+  const int32_t nd = R.nd;
+  const int64_t n = R.n;
+  const double* __restrict__ v0 = val + R.val0 + i;
+  for (int d0 = 0; d0 < nd; d0 += 8) {
     double v[8];
     double2 x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int d = d0 + k;
-      const int64_t j = i + D.off[d < DIA_MAX ? d : 0];
-      const bool ok = d < D.nd && j >= 0 && j < n;
-      v[k] = ok ? ldnt(D.val + (int64_t)d * n + i) : 0.0;
-      x[k] = ok ? src.get((int32_t)j) : make_double2(0.0, 0.0);
+      const int64_t j = i + R.off[d < DIA_MAX ? d : 0];
+      const bool ok = d < nd && j >= 0 && j < n;
+      v[k] = ok ? ldnt(v0 + (int64_t)d * n) : 0.0;
+      x[k] = ok ? src.get((int32_t)(R.row0 + j)) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -87,13 +91,13 @@ __device__ __forceinline__ void dia_row(const DiaView& D, int64_t n, const S& sr
   }
 }
 
-// The row of this thread in a diagonal-storage kernel (one row per thread,
-// blocks of SB_ROWS rows, XCD-aware), or -1.
-__device__ __forceinline__ int64_t dia_thread_row(const CsrView& A) {
+// The block of this workgroup in a diagonal-storage kernel (one row per
+// thread, XCD-aware), or -1, and its system.
+__device__ __forceinline__ int32_t dia_block(const CsrView& A, int32_t& sys) {
   const int32_t bb = xcd_logical(blockIdx.x, gridDim.x);
   if (bb >= A.dia.nblk) return -1;
-  const int64_t i = (int64_t)A.dia.blk[bb] + threadIdx.x;
-  return i < A.dia.blk[bb + 1] ? i : -1;
+  sys = A.dia.bsys ? A.dia.bsys[bb] : 0;
+  return bb;
 }
 
 static int dia_grid(const CsrView& A) {
@@ -208,14 +212,19 @@ __global__ __launch_bounds__(256) void k_sweep(const Ctl* __restrict__ ctls, int
   }
 }
 
-// The same level from the diagonal storage (a single system): one row per
-// thread, every load coalesced, no product buffer and no barrier.
-__global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctl, int level,
+// The same level from the diagonal storage: one row per thread, every load
+// coalesced, no product buffer and no barrier.
+__global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctls, int level,
                                                    CsrView A, double2* __restrict__ pairs,
                                                    int64_t ld) {
+  int32_t sys;
+  const int32_t bb = dia_block(A, sys);
+  if (bb < 0) return;
+  const Ctl* ctl = ctls + sys;
   if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
-  const int64_t i = dia_thread_row(A);
-  if (i < 0) return;
+  const int64_t i = (int64_t)A.dia.blk[bb] + threadIdx.x;
+  if (i >= A.dia.blk[bb + 1]) return;
+  const DiaSys& R = A.dia.sys[sys];
   const double th = ctl->theta[level - 1];
   const double ga = ctl->gamma[level - 1];
   const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctl, 
   double2 x2 = make_double2(0.0, 0.0);
   if (mu != 0.0) x2 = ldnt2(X2 + i);
   double ax, ay;
-  dia_row<2>(A.dia, A.n, Src2{X}, i, ax, ay);
+  dia_row<2>(R, A.dia.val, Src2{X}, i - R.row0, ax, ay);
   double yx = ax - th * xo.x;
   double yy = ay - th * xo.y;
   if (mu != 0.0) {
@@ -279,7 +288,7 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
     ASSG_DCHECK(chunk >= 0 && chunk < A.dia.nchunk, 14);
     b0 = A.dia.cblk[chunk];
     b1 = A.dia.cblk[chunk + 1];
-    sys = 0;
+    sys = A.dia.csys ? A.dia.csys[chunk] : 0;
   } else {
     chunk = chunk_of(A, b0, b1, sys);
   }
@@ -390,7 +399,10 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
               2);   // nt: streamed once
         }
       }
-      if (own) dia_row<1>(A.dia, A.n, SrcP{xsrc}, (int64_t)cur.r0 + tid, a, unused);
+      if (own) {
+        const DiaSys& R = A.dia.sys[sys];
+        dia_row<1>(R, A.dia.val, SrcP{xsrc}, (int64_t)cur.r0 + tid - R.row0, a, unused);
+      }
     } else {
       if (cur.ne <= SB_CAP) {
         if (cur.ne > 0) {
@@ -598,6 +610,7 @@ void launch_gram_reduce(hipStream_t s, Ctl* ctl, int sigma, const CsrView& A,
   if (A.dia.nd > 0) {
     v.nchunk = A.dia.nchunk;
     v.cblk = A.dia.cblk;
+    v.csys = A.dia.csys;
     v.sys_chunk = A.dia.sys_chunk;
   }
   ASSG_SIGMA_SWITCH(sigma, hipLaunchKernelGGL(k_gram_reduce<NC>, dim3(NC * (NC + 1) / 2, v.nsys),
@@ -845,12 +858,15 @@ __global__ __launch_bounds__(256) void k_h_spmv_dia(const Ctl* ctl, CsrView A,
                                                     double* __restrict__ part) {
   if (ctl->status != ST_RUNNING || ctl->pending != ST_RUNNING) return;
   __shared__ double red[4];
-  const int64_t i = dia_thread_row(A);
+  int32_t sys;
+  const int32_t bb = dia_block(A, sys);
+  const int64_t i = bb < 0 ? -1 : (int64_t)A.dia.blk[bb] + threadIdx.x;
   double my = 0.0;
-  if (i >= 0) {
+  if (bb >= 0 && i < A.dia.blk[bb + 1]) {
+    const DiaSys& R = A.dia.sys[sys];
     const double pi = p[i];
     double v, unused;
-    dia_row<1>(A.dia, A.n, Src1{p}, i, v, unused);
+    dia_row<1>(R, A.dia.val, Src1{p}, i - R.row0, v, unused);
     stnt(w + i, v);
     my = pi * v;
   }
@@ -982,19 +998,19 @@ void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, cons
 // ---------------------------------------------------- diagonal storage
 // *flag = 1 (every offending thread stores the same value) unless each
 // row's column offsets c - i are a strictly increasing subsequence of the
-// ascending D.off (sorted, duplicate-free rows whose entries all lie on the
+// ascending R.off (sorted, duplicate-free rows whose entries all lie on the
 // diagonals).
 __global__ __launch_bounds__(256) void k_dia_probe(const int32_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ ci, int64_t n,
-                                                   DiaView D, int32_t* __restrict__ flag) {
+                                                   const int32_t* __restrict__ ci, DiaSys R,
+                                                   int32_t* __restrict__ flag) {
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n && !bad;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < R.n && !bad;
        i += (int64_t)gridDim.x * 256) {
     int d = 0;
     for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
       const int64_t off = (int64_t)ci[e] - i;
-      while (d < D.nd && D.off[d] < off) ++d;
-      if (d >= D.nd || D.off[d] != off) {
+      while (d < R.nd && R.off[d] < off) ++d;
+      if (d >= R.nd || R.off[d] != off) {
         bad = true;
         break;
       }
@@ -1004,12 +1020,12 @@ __global__ __launch_bounds__(256) void k_dia_probe(const int32_t* __restrict__ r
   if (bad) flag[0] = 1;
 }
 
-void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, int64_t n,
-                      const DiaView& D, int32_t* flag) {
-  const int64_t g = (n + 255) / 256;
+void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, const DiaSys& R,
+                      int32_t* flag) {
+  const int64_t g = ((int64_t)R.n + 255) / 256;
   if (g > 0)
     hipLaunchKernelGGL(k_dia_probe, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, rp,
-                       ci, n, D, flag);
+                       ci, R, flag);
 }
 
 // val[d * n + i] = A[i][i + off[d]], or 0.  One workgroup per 64 rows:
@@ -1019,11 +1035,12 @@ void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, int64
 // diagonal (sixteen consecutive rows per wave and diagonal).
 __global__ __launch_bounds__(256) void k_dia_fill(const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci,
-                                                  const double* __restrict__ va, int64_t n,
-                                                  DiaView D, double* __restrict__ val) {
+                                                  const double* __restrict__ va, DiaSys R,
+                                                  double* __restrict__ val) {
   constexpr int RB = 64;
   __shared__ int32_t sc[RB * DIA_MAX];
   __shared__ double sv[RB * DIA_MAX];
+  const int64_t n = R.n;
   const int64_t r0 = (int64_t)blockIdx.x * RB;
   if (r0 >= n) return;
   const int64_t r1 = r0 + RB < n ? r0 + RB : n;
@@ -1040,18 +1057,18 @@ __global__ __launch_bounds__(256) void k_dia_fill(const int32_t* __restrict__ rp
   if (i >= r1) return;
   int32_t e = rp[i] - e0;
   const int32_t e1 = rp[i + 1] - e0;
-  for (int d = 0; d < D.nd; ++d) {
+  for (int d = 0; d < R.nd; ++d) {
     double v = 0.0;
-    if (e < e1 && (int64_t)sc[e] - i == D.off[d]) v = sv[e++];
+    if (e < e1 && (int64_t)sc[e] - i == R.off[d]) v = sv[e++];
     if ((d & 3) == q) stnt(val + (int64_t)d * n + i, v);
   }
 }
 
 void launch_dia_fill(hipStream_t s, const int32_t* rp, const int32_t* ci, const double* va,
-                     int64_t n, const DiaView& D, double* val) {
-  const int64_t g = (n + 63) / 64;
+                     const DiaSys& R, double* val) {
+  const int64_t g = ((int64_t)R.n + 63) / 64;
   if (g > 0)
-    hipLaunchKernelGGL(k_dia_fill, dim3((unsigned)g), dim3(256), 0, s, rp, ci, va, n, D, val);
+    hipLaunchKernelGGL(k_dia_fill, dim3((unsigned)g), dim3(256), 0, s, rp, ci, va, R, val);
 }
 
 // *flag = 1 when a column index of ci[0, nnz) lies outside [0, n) (every

@@ -12,22 +12,32 @@
 
 namespace assg {
 
-// Diagonal storage of a single system whose nonzeros all lie on at most
-// DIA_MAX diagonals (stencil matrices): val[d * n + i] = A[i][i + off[d]],
-// 0 where A has no entry, offsets ascending, so a row's products are added
-// in column order as in the CSR kernels, and no column index or row pointer
-// is read.  Its row kernels take plain blocks of SB_ROWS rows (blk) and its
-// reduction chunks run over those blocks (cblk, sys_chunk).  nd = 0: the
-// matrix is read as CSR.
+// Diagonal storage of stencil matrices: every entry of a system lies on one
+// of at most DIA_MAX diagonals (i, i + off[d]), offsets ascending, and the
+// system's values are val[val0 + d * n + i] for its local row i (0 where A
+// has no entry), so a row's products are added in column order as in the
+// CSR kernels, and no column index or row pointer is read.  The row kernels
+// take blocks of at most SB_ROWS rows that never straddle systems (blk,
+// bsys), and the reduction chunks run over those blocks (cblk, csys,
+// sys_chunk).  nd = 0: the matrix is read as CSR.
 constexpr int DIA_MAX = 32;
-struct DiaView {
-  int32_t nd;
+struct DiaSys {
+  int64_t val0;              // first value of the system in the storage
+  int64_t row0;              // first row of the system (0 for a single system)
+  int32_t n;                 // rows
+  int32_t nd;                // diagonals
   int32_t off[DIA_MAX];
+};
+struct DiaView {
+  int32_t nd;                // the most diagonals of any system; 0: CSR
+  const DiaSys* sys;         // one record per system
   const double* val;
   const int32_t* blk;        // nblk + 1 row starts
+  const int32_t* bsys;       // nblk: system of each block (null: one system)
   int32_t nblk;
   const int32_t* cblk;       // nchunk + 1 first blocks
-  const int32_t* sys_chunk;  // {0, nchunk}
+  const int32_t* csys;       // nchunk: system of each chunk (null: one system)
+  const int32_t* sys_chunk;  // nsys + 1 first chunks
   int32_t nchunk;
 };
 
@@ -50,7 +60,7 @@ struct CsrView {
   const int32_t* sys_chunk;  // nsys + 1: first chunk of each system
   int32_t nchunk;            // a multiple of 8 (trailing chunks may be empty)
   int32_t nsys;
-  DiaView dia;               // diagonal storage of a single system (dia.nd = 0: none)
+  DiaView dia;               // diagonal storage (dia.nd = 0: none)
 };
 
 void launch_spmv(hipStream_t s, const CsrView& A, const double* x, double* y);
@@ -102,14 +112,15 @@ void launch_h_update(hipStream_t s, Ctl* ctl, const CsrView& A, double* x, doubl
 void launch_outer_pattern(hipStream_t s, const CsrView& A, const double* u, const double* v,
                           double alpha, double* out);
 
-// Diagonal storage: *flag = 1 unless every row's column offsets form a
-// strictly increasing subsequence of D.off (flag cleared by the caller);
-// the fill writes D's values (every position, 0 where A has no entry) from
-// the CSR values.
-void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, int64_t n,
-                      const DiaView& D, int32_t* flag);
+// Diagonal storage of one system R (rows of its own CSR arrays): *flag = 1
+// unless every row's column offsets form a strictly increasing subsequence
+// of R.off (flag cleared by the caller); the fill writes the system's values
+// val[d * R.n + i] (val: the storage at R.val0; every position, 0 where A
+// has no entry) from the CSR values.
+void launch_dia_probe(hipStream_t s, const int32_t* rp, const int32_t* ci, const DiaSys& R,
+                      int32_t* flag);
 void launch_dia_fill(hipStream_t s, const int32_t* rp, const int32_t* ci, const double* va,
-                     int64_t n, const DiaView& D, double* val);
+                     const DiaSys& R, double* val);
 
 // *flag = 1 if some ci[e], e < nnz, is outside [0, n) (flag cleared by the caller).
 void launch_check_cols(hipStream_t s, const int32_t* ci, int64_t nnz, int32_t n, int32_t* flag);

@@ -45,6 +45,7 @@ def _random_spd(n, seed):
 
 def test_format_choice(env):
     torch, L, h = env
+    assert L.lib().assg_set_format(h.ptr, 7) == L.ERR_INVALID_ARG
     pr = P.make_config("poisson3d_256", size=20)
     Ad = L.csr_to_device(pr.A)
     assert _analyze(L, h, Ad, "auto") == "dia"
@@ -57,7 +58,6 @@ def test_format_choice(env):
         _analyze(L, h, Rd, "dia")
     with pytest.raises(L.AssgError):            # a failed analysis leaves none behind
         L.assg_get_format(h)
-    assert L.lib().assg_set_format(h.ptr, 7) == L.ERR_INVALID_ARG
     # a tridiagonal matrix with one far pair of entries in a row the
     # analysis does not sample: the probe finds it, AUTO falls back to CSR
     n = 5000
@@ -219,3 +219,68 @@ def test_noalloc_and_forced_schedule_read_the_diagonal_storage(env):
         res[fmt] = (x.cpu().numpy(), i["outer_iters"], xf.cpu().numpy(), jf["outer_iters"])
     assert np.array_equal(res["csr"][0], res["dia"][0]) and res["csr"][1] == res["dia"][1]
     assert np.array_equal(res["csr"][2], res["dia"][2]) and res["csr"][3] == res["dia"][3]
+
+
+def _batch(torch, L, h, probs, fmt, opts, scale=None):
+    As = [L.csr_to_device(pr.A) for pr in probs]
+    L.assg_set_format(h, fmt)
+    try:
+        L.assg_batch_analyze(h, As)
+    finally:
+        L.assg_set_format(h, "auto")
+    got = L.assg_batch_format(h)
+    if scale is not None:                       # values changed after the analysis
+        i, f = scale
+        As[i].val.mul_(f)
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    infos = L.assg_batch_solve(h, As, bs, xs, L.assg_default_opts(**opts))
+    return got, [x.cpu().numpy() for x in xs], infos
+
+
+@pytest.mark.parametrize("basis", ["chebyshev", "newton"])
+def test_batch_in_both_storages(env, basis):
+    """A batch of 2-D Poisson systems of uneven sides takes the diagonal
+    storage (each system with its own diagonals); both storages converge
+    every system to the tolerance with the same outer-loop counts (+-1), and
+    the solutions agree with the oracle's."""
+    torch, L, h = env
+    probs = P.make_batch(count=8, lo=16, hi=120, seed=41)
+    opts = dict(s_max=10, tol=1e-10, basis=basis)
+    fc, xc, ic = _batch(torch, L, h, probs, "csr", opts)
+    fd, xd, id_ = _batch(torch, L, h, probs, "auto", opts)
+    assert fc == "csr" and fd == "dia"
+    for pr, a, b, i, j in zip(probs, xc, xd, ic, id_):
+        assert i["outcome"] == j["outcome"] == L.CONVERGED
+        assert abs(i["outer_iters"] - j["outer_iters"]) <= 1
+        for x in (a, b):
+            assert np.linalg.norm(pr.b - pr.A @ x) / np.linalg.norm(pr.b) <= 1e-10
+        xo, io = O.adaptive_sstep_cg(pr.A, pr.b, pr.x0, s_max=10, tol=1e-10, basis=basis)
+        assert abs(j["outer_iters"] - io["outer"]) <= 1
+        assert np.linalg.norm(b - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_batch_storage_choice_and_refresh(env):
+    """One system off 32 diagonals keeps the whole batch in CSR (AUTO) or
+    fails the forced analysis; values changed after the analysis are the
+    ones solved with."""
+    torch, L, h = env
+    probs = P.make_batch(count=4, lo=20, hi=60, seed=43)
+    R = _random_spd(900, 9)
+    rhs = P.rhs_normal(900, 5)
+    mixed = list(probs) + [P.Problem(name="random", A=R, b=rhs, x0=np.zeros(900))]
+    got, xs, infos = _batch(torch, L, h, mixed, "auto", dict(tol=1e-10))
+    assert got == "csr" and all(i["outcome"] == L.CONVERGED for i in infos)
+    with pytest.raises(L.AssgError, match="unsupported"):
+        _batch(torch, L, h, mixed, "dia", dict(tol=1e-10))
+    with pytest.raises(L.AssgError):
+        L.assg_batch_format(h)
+    opts = dict(s_max=10, tol=1e-10)
+    fd, xd, id_ = _batch(torch, L, h, probs, "dia", opts, scale=(2, 4.0))
+    fc, xc, ic = _batch(torch, L, h, probs, "csr", opts, scale=(2, 4.0))
+    assert fd == "dia" and fc == "csr"
+    A2 = probs[2].A * 4.0
+    for k, (pr, a, b) in enumerate(zip(probs, xc, xd)):
+        M = A2 if k == 2 else pr.A
+        for x in (a, b):
+            assert np.linalg.norm(pr.b - M @ x) / np.linalg.norm(pr.b) <= 1e-10
