@@ -62,23 +62,32 @@ struct BlockRows {
 // added, as a sequential CSR product adds them; a diagonal position without
 // an entry of A holds 0 and adds +0, which leaves the sum unchanged.  Eight
 // diagonals' loads are issued before their products are added.  src is
-// indexed by the batch row (R.row0 + column).
+// indexed by the batch row (R.row0 + column).  The record is read through
+// the constant address space, so its fields come through the scalar cache
+// (the same for every lane) and no vector load stands between a row and its
+// diagonals' addresses.
+typedef const __attribute__((address_space(4))) DiaSys kDiaSys;
 template <int CH, class S>
-__device__ __forceinline__ void dia_row(const DiaSys& R, const double* __restrict__ val,
+__device__ __forceinline__ void dia_row(const DiaSys* Rp, const double* __restrict__ val,
                                         const S& src, int64_t i, double& sx, double& sy) {
 #pragma clang fp contract(off)
+  const kDiaSys& R = *(const kDiaSys*)Rp;
   sx = 0.0;
   sy = 0.0;
   const int32_t nd = R.nd;
   const int64_t n = R.n;
   const double* __restrict__ v0 = val + R.val0 + i;
+  static_assert(DIA_MAX % 8 == 0, "diagonals are taken eight at a time");
   for (int d0 = 0; d0 < nd; d0 += 8) {
+    int32_t off[8];                           // one batch of scalar loads
+#pragma unroll
+    for (int k = 0; k < 8; ++k) off[k] = R.off[d0 + k];
     double v[8];
     double2 x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int d = d0 + k;
-      const int64_t j = i + R.off[d < DIA_MAX ? d : 0];
+      const int64_t j = i + off[k];
       const bool ok = d < nd && j >= 0 && j < n;
       v[k] = ok ? ldnt(v0 + (int64_t)d * n) : 0.0;
       x[k] = ok ? src.get((int32_t)(R.row0 + j)) : make_double2(0.0, 0.0);
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctls,
   if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
   const int64_t i = (int64_t)A.dia.blk[bb] + threadIdx.x;
   if (i >= A.dia.blk[bb + 1]) return;
-  const DiaSys& R = A.dia.sys[sys];
+  const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
   const double th = ctl->theta[level - 1];
   const double ga = ctl->gamma[level - 1];
   const double mu = (level >= 2) ? ctl->mu[level - 2] : 0.0;
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctls,
   double2 x2 = make_double2(0.0, 0.0);
   if (mu != 0.0) x2 = ldnt2(X2 + i);
   double ax, ay;
-  dia_row<2>(R, A.dia.val, Src2{X}, i - R.row0, ax, ay);
+  dia_row<2>(A.dia.sys + sys, A.dia.val, Src2{X}, i - R.row0, ax, ay);
   double yx = ax - th * xo.x;
   double yy = ay - th * xo.y;
   if (mu != 0.0) {
@@ -400,8 +409,9 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
         }
       }
       if (own) {
-        const DiaSys& R = A.dia.sys[sys];
-        dia_row<1>(R, A.dia.val, SrcP{xsrc}, (int64_t)cur.r0 + tid - R.row0, a, unused);
+        const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
+        dia_row<1>(A.dia.sys + sys, A.dia.val, SrcP{xsrc}, (int64_t)cur.r0 + tid - R.row0, a,
+                   unused);
       }
     } else {
       if (cur.ne <= SB_CAP) {
@@ -863,10 +873,10 @@ __global__ __launch_bounds__(256) void k_h_spmv_dia(const Ctl* ctl, CsrView A,
   const int64_t i = bb < 0 ? -1 : (int64_t)A.dia.blk[bb] + threadIdx.x;
   double my = 0.0;
   if (bb >= 0 && i < A.dia.blk[bb + 1]) {
-    const DiaSys& R = A.dia.sys[sys];
+    const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
     const double pi = p[i];
     double v, unused;
-    dia_row<1>(R, A.dia.val, Src1{p}, i - R.row0, v, unused);
+    dia_row<1>(A.dia.sys + sys, A.dia.val, Src1{p}, i - R.row0, v, unused);
     stnt(w + i, v);
     my = pi * v;
   }
