@@ -239,6 +239,38 @@ def main():
         methods["newton"]["sweep_avg_ms"] = round(nav, 4)
         methods["newton"]["sweep_GBps"] = round(sweep_nb / (nav * 1e-3) / 1e9, 1)
 
+    if not args.no_compare and fmt != "csr":
+        # the same three methods with the CSR storage forced (A read as it is
+        # handed over), the same protocol, on a handle of its own
+        h2 = L.assg_create()
+        L.assg_set_format(h2, "csr")
+        L.assg_analyze(h2, A)
+
+        def solve_csr(basis):
+            x.zero_()
+            return L.assg_solve(h2, A, b, x, L.assg_default_opts(
+                s_max=sigma, s_init=sigma, growth=sigma, tol=tol, basis=basis,
+                max_iters=max_iters))
+
+        def hscg_csr():
+            x.zero_()
+            return L.assg_hscg_solve(h2, A, b, x, tol, max_iters)
+
+        tc2, ic2 = time_solves(lambda: solve_csr("chebyshev"), args.warmup, args.steps, torch)
+        tn2, in2 = time_solves(lambda: solve_csr("newton"), args.warmup, args.steps, torch)
+        th2, ih2 = time_solves(hscg_csr, args.warmup, args.steps, torch)
+        extra["csr_storage"] = {
+            "format": L.assg_get_format(h2), "matrix_bytes": matrix_bytes(pr.A, "csr"),
+            "chebyshev": summary(tc2, ic2), "newton": summary(tn2, in2),
+            "hscg": summary(th2, ih2),
+            "speedup_vs_hscg": {
+                "chebyshev": round(float(np.median(th2)) / float(np.median(tc2)), 3),
+                "newton": round(float(np.median(th2)) / float(np.median(tn2)), 3)}}
+        print(f"[bench] CSR storage, median wall: chebyshev {np.median(tc2)*1e3:.1f} ms, newton "
+              f"{np.median(tn2)*1e3:.1f} ms, hscg {np.median(th2)*1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+        L.assg_destroy(h2)
+
     if not args.no_small:
         extra["poisson2d_64"] = bench_small(L, P, torch, args.warmup, args.steps)
     if not args.no_diffusion:
