@@ -65,11 +65,18 @@ struct BlockRows {
 // indexed by the batch row (R.row0 + column).  The record is read through
 // the constant address space, so its fields come through the scalar cache
 // (the same for every lane) and no vector load stands between a row and its
-// diagonals' addresses.
+// diagonals' addresses.  With SHIFT, within a run of consecutive offsets
+// (off_d = off_{d-1} + 1, as the x-neighbours of a stencil) row i's source
+// entry for diagonal d is row i + 1's for diagonal d - 1: lane l takes it
+// from lane l + 1 by a wave shift instead of a gather, and lane 63, whose
+// neighbour row lies in the next wave, loads it.  Then every lane of the
+// wave calls this; a lane whose row lies past its block (row_ok false)
+// gathers for its neighbour but loads no values, and its sums are not used.
 typedef const __attribute__((address_space(4))) DiaSys kDiaSys;
-template <int CH, class S>
+template <int CH, bool SHIFT, class S>
 __device__ __forceinline__ void dia_row(const DiaSys* Rp, const double* __restrict__ val,
-                                        const S& src, int64_t i, double& sx, double& sy) {
+                                        const S& src, int64_t i, bool row_ok, double& sx,
+                                        double& sy) {
 #pragma clang fp contract(off)
   const kDiaSys& R = *(const kDiaSys*)Rp;
   sx = 0.0;
@@ -77,11 +84,18 @@ __device__ __forceinline__ void dia_row(const DiaSys* Rp, const double* __restri
   const int32_t nd = R.nd;
   const int64_t n = R.n;
   const double* __restrict__ v0 = val + R.val0 + i;
+  const bool lane63 = (threadIdx.x & 63) == 63;
+  int32_t prev = 0;                           // offset of the previous diagonal
+  double2 xprev = make_double2(0.0, 0.0);     // and this lane's source entry for it
   static_assert(DIA_MAX % 8 == 0, "diagonals are taken eight at a time");
   for (int d0 = 0; d0 < nd; d0 += 8) {
     int32_t off[8];                           // one batch of scalar loads
 #pragma unroll
     for (int k = 0; k < 8; ++k) off[k] = R.off[d0 + k];
+    bool run[8];                              // continues the previous diagonal's run
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      run[k] = SHIFT && d0 + k < nd && d0 + k > 0 && off[k] == (k == 0 ? prev : off[k - 1]) + 1;
     double v[8];
     double2 x[8];
 #pragma unroll
@@ -89,14 +103,25 @@ __device__ __forceinline__ void dia_row(const DiaSys* Rp, const double* __restri
       const int d = d0 + k;
       const int64_t j = i + off[k];
       const bool ok = d < nd && j >= 0 && j < n;
-      v[k] = ok ? ldnt(v0 + (int64_t)d * n) : 0.0;
-      x[k] = ok ? src.get((int32_t)(R.row0 + j)) : make_double2(0.0, 0.0);
+      v[k] = (ok && row_ok) ? ldnt(v0 + (int64_t)d * n) : 0.0;
+      x[k] = (ok && (!run[k] || lane63)) ? src.get((int32_t)(R.row0 + j)) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (run[k]) {
+        const double2 pv = (k == 0) ? xprev : x[k - 1];
+        const double sxv = wave_shl1_d(pv.x);
+        const double syv = (CH == 2) ? wave_shl1_d(pv.y) : 0.0;
+        if (!lane63) x[k] = make_double2(sxv, syv);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       sx += v[k] * x[k].x;
       if constexpr (CH == 2) sy += v[k] * x[k].y;
     }
+    xprev = x[7];
+    prev = off[7];
   }
 }
 
@@ -231,8 +256,10 @@ __global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctls,
   if (bb < 0) return;
   const Ctl* ctl = ctls + sys;
   if (ctl->status != ST_RUNNING || level >= ctl->sbar) return;
+  // every lane takes part in the row products (rows past the block only
+  // gather for their neighbours)
   const int64_t i = (int64_t)A.dia.blk[bb] + threadIdx.x;
-  if (i >= A.dia.blk[bb + 1]) return;
+  const bool own = i < A.dia.blk[bb + 1];
   const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
   const double th = ctl->theta[level - 1];
   const double ga = ctl->gamma[level - 1];
@@ -240,11 +267,12 @@ __global__ __launch_bounds__(256) void k_sweep_dia(const Ctl* __restrict__ ctls,
   const double2* __restrict__ X = pairs + (size_t)(level - 1) * ld;
   const double2* __restrict__ X2 = pairs + (size_t)(level >= 2 ? level - 2 : 0) * ld;
   double2* __restrict__ Yo = pairs + (size_t)level * ld;
+  double ax, ay;
+  dia_row<2, true>(A.dia.sys + sys, A.dia.val, Src2{X}, i - R.row0, own, ax, ay);
+  if (!own) return;
   const double2 xo = X[i];
   double2 x2 = make_double2(0.0, 0.0);
   if (mu != 0.0) x2 = ldnt2(X2 + i);
-  double ax, ay;
-  dia_row<2>(A.dia.sys + sys, A.dia.val, Src2{X}, i - R.row0, ax, ay);
   double yx = ax - th * xo.x;
   double yy = ay - th * xo.y;
   if (mu != 0.0) {
@@ -408,10 +436,10 @@ void k_last_gram(const Ctl* __restrict__ ctls, CsrView A, const double2* __restr
               2);   // nt: streamed once
         }
       }
-      if (own) {
+      if (own) {   // plain gathers: the wave shift measured slower here
         const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
-        dia_row<1>(A.dia.sys + sys, A.dia.val, SrcP{xsrc}, (int64_t)cur.r0 + tid - R.row0, a,
-                   unused);
+        dia_row<1, false>(A.dia.sys + sys, A.dia.val, SrcP{xsrc}, (int64_t)cur.r0 + tid - R.row0,
+                          true, a, unused);
       }
     } else {
       if (cur.ne <= SB_CAP) {
@@ -872,13 +900,15 @@ __global__ __launch_bounds__(256) void k_h_spmv_dia(const Ctl* ctl, CsrView A,
   const int32_t bb = dia_block(A, sys);
   const int64_t i = bb < 0 ? -1 : (int64_t)A.dia.blk[bb] + threadIdx.x;
   double my = 0.0;
-  if (bb >= 0 && i < A.dia.blk[bb + 1]) {
+  if (bb >= 0) {   // every lane: rows past the block gather for their neighbours
+    const bool own = i < A.dia.blk[bb + 1];
     const kDiaSys& R = *(const kDiaSys*)(A.dia.sys + sys);
-    const double pi = p[i];
     double v, unused;
-    dia_row<1>(A.dia.sys + sys, A.dia.val, Src1{p}, i - R.row0, v, unused);
-    stnt(w + i, v);
-    my = pi * v;
+    dia_row<1, true>(A.dia.sys + sys, A.dia.val, Src1{p}, i - R.row0, own, v, unused);
+    if (own) {
+      stnt(w + i, v);
+      my = p[i] * v;
+    }
   }
   my = block_sum<256>(my, red);
   if (threadIdx.x == 0) part[blockIdx.x] = my;
