@@ -112,6 +112,43 @@ def test_basis_and_gram_equal_csr(env, name, size, same_blocks, s):
     assert np.max(np.abs(Gd - Gr) / sc) <= 1e-12
 
 
+def _banded_spd(n, offsets, seed):
+    """Symmetric matrix with full diagonals at the given positive offsets
+    (and their mirrors), random off-diagonal values and a dominant diagonal:
+    SPD."""
+    rng = np.random.default_rng(seed)
+    A = sp.diags([np.full(n, 2.0 * len(offsets) + 1.0)], [0], format="lil").tocsr()
+    for o in offsets:
+        v = rng.uniform(-1.0, 1.0, n - o)
+        A = A + sp.diags([v, v], [o, -o], shape=(n, n), format="csr")
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("s", [4, 10])
+def test_irregular_diagonals_bit_identical_to_csr(env, s):
+    """Offsets with runs of consecutive diagonals of several lengths (whose
+    source entries the sweeps pass between lanes), runs that cross the groups
+    of eight diagonals the kernels load at a time, isolated diagonals, and a
+    ragged row count: every basis row equals the CSR kernels' bit for bit,
+    and the Gram matrix matches Y^T Y."""
+    torch, L, h = env
+    n = 3001
+    A = _banded_spd(n, [1, 6, 7, 50, 297, 298, 299, 300], seed=11)
+    offs = np.unique(np.concatenate([A.indices[A.indptr[i]:A.indptr[i + 1]] - i
+                                     for i in (0, 1500, n - 1)]))
+    assert len(offs) == 17
+    Ad = L.csr_to_device(A)
+    assert _analyze(L, h, Ad, "auto") == "dia"
+    Gc, Yc = _basis_gram(torch, L, h, Ad, n, s, "csr", seed=5)
+    Gd, Yd = _basis_gram(torch, L, h, Ad, n, s, "dia", seed=5)
+    assert np.array_equal(Yc, Yd)
+    sc = np.sqrt(np.outer(np.diag(Gc), np.diag(Gc)))
+    assert np.max(np.abs(Gd - Gc) / sc) <= 1e-14
+    assert np.max(np.abs(Gd - Yd @ Yd.T) / sc) <= 1e-12
+
+
 def _solve(torch, L, h, pr, fmt, **opts):
     Ad = L.csr_to_device(pr.A)
     assert _analyze(L, h, Ad, fmt) == fmt
