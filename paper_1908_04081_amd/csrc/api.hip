@@ -243,25 +243,21 @@ void refresh_dia(assg_handle_t h, const assg_csr_t* A) {
     launch_dia_fill(h->stream, A->row_ptr, A->col_idx, A->val, h->dia.rec[0], h->dia.val);
 }
 
-// The offsets of 64 rows spread over the matrix by the golden-ratio
-// sequence (evenly spaced fractions of n land on the boundary planes of
-// power-of-two grids and miss diagonals) are the candidates; a kernel then
-// checks that every row's entries lie on them, in order.
+// The offsets of the sampled rows (dia_sample_rows) are the candidates
+// (dia_offsets); a kernel then checks that every row's entries lie on them,
+// in order.
 assg_status_t dia_detect(assg_handle_t h, const assg_csr_t* A, const int32_t* rp, bool check_fill,
                          DiaSys* R, bool* fits, std::string* why) {
   *fits = false;
   const int64_t n = A->n;
-  std::vector<int64_t> offs;
-  constexpr int NS = 64;
+  std::vector<int64_t> rows, offs;
+  dia_sample_rows(n, rows);
   std::vector<int32_t> cols;
-  for (int k = 0; k < NS; ++k) {
-    const double f = std::fmod(0.5 + 0.6180339887498949 * k, 1.0);
-    const int64_t i = std::min<int64_t>(n - 1, (int64_t)(f * (double)n));
+  int64_t max_row = 0;
+  for (const int64_t i : rows) {
     const int32_t e0 = rp[i], e1 = rp[i + 1];
-    if (e1 - e0 > DIA_MAX) {
-      *why = "a row has more than 32 entries";
-      return ASSG_OK;
-    }
+    max_row = std::max<int64_t>(max_row, e1 - e0);
+    if (e1 - e0 > DIA_MAX) break;
     cols.resize(e1 - e0);
     if (e1 > e0) {
       HIP_OR_FAIL(h, hipMemcpyAsync(cols.data(), A->col_idx + e0, (e1 - e0) * sizeof(int32_t),
@@ -270,14 +266,8 @@ assg_status_t dia_detect(assg_handle_t h, const assg_csr_t* A, const int32_t* rp
     }
     for (int32_t c : cols) offs.push_back((int64_t)c - i);
   }
-  std::sort(offs.begin(), offs.end());
-  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
-  if (offs.empty() || (int)offs.size() > DIA_MAX) {
-    *why = "more than 32 diagonals";
-    return ASSG_OK;
-  }
-  if (check_fill && (double)offs.size() * (double)n > 1.15 * (double)A->nnz) {
-    *why = "the diagonals hold more than 15% more positions than A has entries";
+  if (const char* no = dia_offsets(offs, max_row, n, A->nnz, check_fill)) {
+    *why = no;
     return ASSG_OK;
   }
   *R = DiaSys{};

@@ -19,8 +19,7 @@ namespace assg {
 // CSR kernels, and no column index or row pointer is read.  The row kernels
 // take blocks of at most SB_ROWS rows that never straddle systems (blk,
 // bsys), and the reduction chunks run over those blocks (cblk, csys,
-// sys_chunk).  nd = 0: the matrix is read as CSR.
-constexpr int DIA_MAX = 32;
+// sys_chunk).  nd = 0: the matrix is read as CSR.  DIA_MAX: partition.hpp.
 struct DiaSys {
   int64_t val0;              // first value of the system in the storage
   int64_t row0;              // first row of the system (0 for a single system)

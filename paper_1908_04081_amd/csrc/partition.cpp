@@ -1,6 +1,9 @@
 // Row-block and reduction-chunk partitions (see partition.hpp).
 #include "partition.hpp"
 
+#include <algorithm>
+#include <cmath>
+
 namespace assg {
 
 void make_blocks(const int32_t* rp, int64_t n, std::vector<int32_t>& blk, int rows, int cap) {
@@ -39,6 +42,26 @@ void make_chunks(const std::vector<int32_t>& sys_blk, int target, std::vector<in
     csys.push_back(nsys - 1);
   }
   cblk.push_back((int32_t)nblk);
+}
+
+void dia_sample_rows(int64_t n, std::vector<int64_t>& rows) {
+  rows.clear();
+  for (int k = 0; k < DIA_SAMPLE; ++k) {
+    const double f = std::fmod(0.5 + 0.6180339887498949 * k, 1.0);
+    const int64_t i = (int64_t)(f * (double)n);
+    rows.push_back(i < n - 1 ? i : n - 1);
+  }
+}
+
+const char* dia_offsets(std::vector<int64_t>& offs, int64_t max_row, int64_t n, int64_t nnz,
+                        bool check_fill) {
+  if (max_row > DIA_MAX) return "a row has more than 32 entries";
+  std::sort(offs.begin(), offs.end());
+  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+  if (offs.empty() || (int64_t)offs.size() > DIA_MAX) return "more than 32 diagonals";
+  if (check_fill && (double)offs.size() * (double)n > 1.15 * (double)nnz)
+    return "the diagonals hold more than 15% more positions than A has entries";
+  return nullptr;
 }
 
 size_t reduce_doubles(int32_t nblk) {

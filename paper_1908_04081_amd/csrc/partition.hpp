@@ -36,4 +36,24 @@ void make_chunks(const std::vector<int32_t>& sys_blk, int target, std::vector<in
 // (two sums for the HSCG start).
 size_t reduce_doubles(int32_t nblk);
 
+// Diagonal storage: at most DIA_MAX diagonals per system.
+constexpr int DIA_MAX = 32;
+constexpr int DIA_SAMPLE = 64;
+
+// The DIA_SAMPLE rows of [0, n) whose column offsets are the candidate
+// diagonals: fractions of n spread by the golden-ratio sequence (evenly
+// spaced fractions land on the boundary planes of power-of-two grids, whose
+// rows lack some diagonals).  n >= 1.
+void dia_sample_rows(int64_t n, std::vector<int64_t>& rows);
+
+// The candidate diagonals from the column offsets (column - row) of the
+// sampled rows' entries: sorted and duplicate-free in ``offs``.  Returns
+// nullptr when they qualify, else the reason: a sampled row with more than
+// DIA_MAX entries (``max_row`` is the longest sampled row), no entries, more
+// than DIA_MAX diagonals, or, with ``check_fill``, diagonals whose n
+// positions each exceed the nnz entries of A by more than 15%.  Whether every
+// row's entries lie on them is checked on the device afterwards.
+const char* dia_offsets(std::vector<int64_t>& offs, int64_t max_row, int64_t n, int64_t nnz,
+                        bool check_fill);
+
 }  // namespace assg

@@ -5,7 +5,9 @@ undefined-behaviour sanitizers and checked for their invariants on random
 row-length patterns and batches: the blocks cover the rows in order, each
 holds at most ``rows`` rows and at most ``cap`` nonzeros or is a single
 row, no block or chunk straddles a system, the chunk count is a multiple of
-8 and at most 4096 (the size of the partial-sum buffers)."""
+8 and at most 4096 (the size of the partial-sum buffers).  Also the host
+part of the diagonal-storage choice: the sampled rows and the candidate
+diagonals taken from them, with the limits that reject a matrix."""
 import os
 import shutil
 import subprocess
@@ -108,3 +110,82 @@ def test_chunks(driver, seed):
         assert nchunk <= max(target, nsys) + 8 + nsys
     if nsys <= 2048 and target <= 768:
         assert nchunk <= 4096
+
+
+# ---- candidate diagonals of the diagonal storage (host part of the choice)
+
+def _dia(driver, A, check_fill=True):
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    text = (f"D {n} {A.nnz} {int(check_fill)}\n" + " ".join(map(str, A.indptr)) + "\n"
+            + " ".join(map(str, A.indices)) + "\n")
+    out = _run(driver, text)[0].strip()
+    rows, res = out.split("|")
+    rows = [int(v) for v in rows.split()]
+    res = res.split()
+    return rows, (res[0] == "ok"), ([int(v) for v in res[1:]] if res[0] == "ok" else " ".join(res[1:]))
+
+
+def _stencil(shape, offsets):
+    import spd_problems as P
+    return P._stencil_csr(shape, offsets, [1.0] * len(offsets))
+
+
+def test_dia_sample_rows_spread(driver):
+    """64 rows inside [0, n), distinct once n leaves room (the first 64
+    golden-ratio fractions lie at least 1/200 apart), and on a 64^3 grid
+    mostly interior rows: the fractions spread over the range instead of
+    hitting multiples of n/64, every one of which is a boundary row there."""
+    import scipy.sparse as sp
+    for n in (1, 5, 64, 4096, 262144, 3001):
+        rows, _, _ = _dia(driver, sp.identity(n, format="csr"))
+        assert len(rows) == 64 and min(rows) >= 0 and max(rows) < n
+        if n >= 4096:
+            assert len(set(rows)) == 64
+    g = 64
+    rows, _, _ = _dia(driver, sp.identity(g ** 3, format="csr"))
+    interior = [r for r in rows if 0 < r // (g * g) < g - 1 and 0 < (r // g) % g < g - 1
+                and 0 < r % g < g - 1]
+    assert len(interior) >= 48
+
+
+@pytest.mark.parametrize("g", [16, 64])
+def test_dia_offsets_of_stencils(driver, g):
+    """The 7- and 27-point stencils give their 7 and 27 offsets, sorted; the
+    27-point stencil on a small grid exceeds the fill limit (its boundary
+    rows leave many positions empty) unless the check is off."""
+    seven = [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 0), (0, 0, 1), (0, 1, 0), (1, 0, 0)]
+    _, ok, offs = _dia(driver, _stencil((g, g, g), seven))
+    assert ok and offs == [-g * g, -g, -1, 0, 1, g, g * g]
+    full = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    A = _stencil((g, g, g), full)
+    lin = sorted(a * g * g + b * g + c for a, b, c in full)
+    rows, ok, offs = _dia(driver, A, check_fill=(g == 64))
+    assert ok and offs == lin
+    if g == 16:
+        _, ok, why = _dia(driver, A, check_fill=True)
+        fill = 27 * g ** 3 / A.nnz
+        assert (not ok and "15%" in why) == (fill > 1.15), fill
+
+
+def test_dia_offsets_rejections(driver):
+    """More than 32 entries in a sampled row, more than 32 diagonals over the
+    sampled rows, and a matrix without entries in its sampled rows."""
+    import scipy.sparse as sp
+    n = 4000
+    dense_row = sp.lil_matrix((n, n))
+    dense_row.setdiag(1.0)
+    rows, _, _ = _dia(driver, sp.identity(n, format="csr"))
+    for c in range(40):
+        dense_row[rows[3], (rows[3] + 1 + c) % n] = 1.0
+    _, ok, why = _dia(driver, dense_row.tocsr())
+    assert not ok and "more than 32 entries" in why
+    # each sampled row on its own offset: 64 diagonals
+    A = sp.lil_matrix((n, n))
+    for k, r in enumerate(rows):
+        A[r, (r + 7 * k + 1) % n] = 1.0
+    _, ok, why = _dia(driver, A.tocsr(), check_fill=False)
+    assert not ok and "more than 32 diagonals" in why
+    _, ok, why = _dia(driver, sp.csr_matrix((n, n)), check_fill=False)
+    assert not ok
