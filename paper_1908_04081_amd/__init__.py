@@ -355,6 +355,34 @@ def assg_solve(h: Handle, A: DeviceCSR, b, x, opts: AssgOpts | None = None, work
     return _info_dict(info)
 
 
+def solve(A, b, x0=None, format: str = "auto", **opts):
+    """One call: analysis and Algorithm 5 on a handle of its own.  A: a
+    DeviceCSR or a scipy CSR matrix (copied to the GPU); b and x0: CUDA
+    float64 tensors or arrays (copied to the GPU); x0 = None starts from 0.
+    ``opts`` are assg_default_opts' keywords.  Returns (x, info) with x a
+    CUDA tensor.  For repeated solves with one pattern keep a handle
+    (assg_create, assg_analyze once, assg_solve per right-hand side)."""
+    import torch
+    if not isinstance(A, DeviceCSR):
+        A = csr_to_device(A)
+    dev = A.val.device
+
+    def on_dev(v):
+        v = torch.as_tensor(v, dtype=torch.float64)
+        return v.to(dev).contiguous()
+
+    b = on_dev(b)
+    x = torch.zeros_like(b) if x0 is None else on_dev(x0).clone()
+    h = assg_create()
+    try:
+        assg_set_format(h, format)
+        assg_analyze(h, A)
+        info = assg_solve(h, A, b, x, assg_default_opts(**opts))
+    finally:
+        assg_destroy(h)
+    return x, info
+
+
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 

@@ -481,6 +481,25 @@ def test_nan_in_rhs_diverges(env):
     assert gh["outcome"] == L.DIVERGED and ih["outcome"] == O.Outcome.DIVERGED
 
 
+def test_one_call_solve_matches_the_handle_calls(env):
+    """solve(A, b) with a scipy matrix and host arrays gives the handle
+    calls' solution bit for bit, with x0 taken when given, and the storage
+    choice passed through."""
+    torch, L, h = env
+    pr = _problem("poisson2d_45")
+    xg, ig = _solve_gpu(torch, L, h, pr, s_max=10, tol=1e-10)
+    x1, i1 = L.solve(pr.A, pr.b, s_max=10, tol=1e-10)
+    assert x1.is_cuda and x1.dtype == torch.float64
+    assert np.array_equal(x1.cpu().numpy(), xg)
+    assert (i1["outer_iters"], i1["total_iters"]) == (ig["outer_iters"], ig["total_iters"])
+    x0 = np.full(pr.n, 0.25)
+    x2, i2 = L.solve(L.csr_to_device(pr.A), torch.from_numpy(pr.b).cuda(), x0=x0,
+                     format="csr", s_max=10, tol=1e-10)
+    assert i2["outcome_name"] == "CONVERGED"
+    assert np.linalg.norm(pr.b - pr.A @ x2.cpu().numpy()) / np.linalg.norm(pr.b) <= 1e-10
+    assert i2["outer_iters"] != 0 and not np.array_equal(x2.cpu().numpy(), xg)
+
+
 def test_assg_log_prints_one_line_per_solve():
     """ASSG_LOG=1 makes the library print one line per finished solve on
     stderr (host side only); without it nothing is printed."""
